@@ -1,0 +1,309 @@
+"""Benchmark of the SPMD kernel-grid executor on one MI355X.
+
+One step = one pass of the warp-primitive workload through the C ABI:
+  * SCAN_I32 over 2^26 int32 uniform in [0, 100], blockDim 512 (16 items
+    per thread, single pass with decoupled look-back), then
+  * HIST256_U32 over 2^27 uint32 keys drawn Zipf(1.1) over 256 bins with
+    per-block LDS sub-histograms.
+Algorithmic bytes per step: 8 B per scanned element (read x, write y) +
+4 B per key + the 1 KiB histogram.  Inputs are generated once (seeded),
+resident in HBM before timing, and rotated between two copies so that each
+step reads data the previous step did not touch (the rotation set is larger
+than the 256 MB Infinity Cache).
+
+Printed: one JSON line (metric, value = GB/s of the whole step, roofline of
+the dominant kernel measured with HIP events on the launch stream, the CPU
+oracle on the same workload, and per-kernel figures of the other
+workloads: the block reduction, the Jacobi stencil and the fp32 GEMM).
+Progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP32_MFMA_PEAK_TFS = 157.3     # MI355X dense fp32 matrix
+
+SCAN_N = 1 << 26
+HIST_N = 1 << 27
+SCAN_BLOCK, SCAN_ITEMS = 512, 16
+HIST_GRID, HIST_BLOCK = 1024, 512
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+class Timer:
+    """HIP events recorded on torch's current stream, which is the stream
+    every launch of this benchmark goes to."""
+
+    def __init__(self):
+        import torch
+
+        self.torch = torch
+        self.pairs = []
+
+    def start(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    def stop(self, s):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.pairs.append((s, e))
+
+    def mean_ms(self):
+        return sum(s.elapsed_time(e) for s, e in self.pairs) / max(1, len(self.pairs))
+
+
+def measure(fn, reps, warmup=2):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t = Timer()
+    for _ in range(reps):
+        s = t.start()
+        fn()
+        t.stop(s)
+    torch.cuda.synchronize()
+    return t.mean_ms()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each kernel class would shard over GPUs as described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2206_07896_amd as spmd
+    import synth
+
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+
+    log("generating inputs")
+    xs_h = synth.uniform_int32(synth.SEED_SCAN, SCAN_N, 0, 100)
+    ks_h = synth.zipf_u32(synth.SEED_HIST, HIST_N)
+    xs = [to_dev(xs_h), to_dev(xs_h)]
+    ks = [to_dev(ks_h), to_dev(ks_h)]
+    ys = [torch.empty_like(xs[0]) for _ in range(2)]
+    hist = torch.empty(256, dtype=torch.int32, device="cuda")
+    scan_grid = spmd.ops.scan_grid(SCAN_N, SCAN_BLOCK, SCAN_ITEMS)
+    ws = spmd.ops.workspace(spmd.SCAN_I32, scan_grid, SCAN_BLOCK, SCAN_N)
+
+    t_scan, t_hist = Timer(), Timer()
+
+    def step(i):
+        s = t_scan.start()
+        spmd.ops.scan_i32(xs[i & 1], SCAN_BLOCK, SCAN_ITEMS, y=ys[i & 1], ws=ws)
+        t_scan.stop(s)
+        s = t_hist.start()
+        spmd.ops.hist256_u32(ks[i & 1], HIST_GRID, HIST_BLOCK, hist=hist)
+        t_hist.stop(s)
+
+    for i in range(args.warmup):
+        step(i)
+    spmd.sync()
+    t_scan.pairs.clear()
+    t_hist.pairs.clear()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    spmd.sync()  # raises if a kernel reported a device-side error
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # spot check of the last step's outputs (full parity lives in the tests)
+    last = (args.warmup + args.steps - 1) & 1
+    y = ys[last].cpu().numpy().view(np.uint32)
+    assert int(y[-1]) == int(xs_h.astype(np.int64).sum()) % 2**32
+    h = hist.cpu().numpy().view(np.uint32)
+    assert int(h.astype(np.int64).sum()) == HIST_N
+
+    scan_bytes = 8 * SCAN_N
+    hist_bytes = 4 * HIST_N + 1024
+    step_bytes = scan_bytes + hist_bytes
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    ms_scan, ms_hist = t_scan.mean_ms(), t_hist.mean_ms()
+    scan_gbs = scan_bytes / (ms_scan * 1e-3) / 1e9
+    hist_gbs = hist_bytes / (ms_hist * 1e-3) / 1e9
+    log(f"step {ms_per_step:.4f} ms  scan {ms_scan * 1e3:.1f} us {scan_gbs:.0f} GB/s  "
+        f"hist {ms_hist * 1e3:.1f} us {hist_gbs:.0f} GB/s")
+    if ms_scan >= ms_hist:
+        dom = ("scan_i32_kernel<512,16>", scan_bytes, ms_scan, scan_gbs)
+    else:
+        dom = ("hist256_kernel<512>", hist_bytes, ms_hist, hist_gbs)
+    roofline = {
+        "kernel": dom[0],
+        "bound": "hbm",
+        "achieved": round(dom[3], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(dom[3] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_launch": dom[1],
+        "avg_launch_us": round(dom[2] * 1e3, 2),
+    }
+
+    kernels = {
+        "scan_i32 2^26 b512": {"us": round(ms_scan * 1e3, 2), "GB/s": round(scan_gbs, 1),
+                               "frac_hbm": round(scan_gbs / HBM_PEAK_GBS, 4)},
+        "hist256_u32 2^27 zipf1.1 g1024 b512": {"us": round(ms_hist * 1e3, 2), "GB/s": round(hist_gbs, 1),
+                                                "frac_hbm": round(hist_gbs / HBM_PEAK_GBS, 4)},
+    }
+    del xs, ks, ys
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        kernels.update(extra_workloads(spmd, synth))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(xs_h, ks_h, step_bytes)
+
+    out = {
+        "metric": "GB/s & % HBM peak per kernel; mixed-queue launches/s, persistent vs 1-by-1",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded SplitMix64: uniform int32 [0,100], Zipf(1.1) keys)",
+        "config": {
+            "workload": "warp-primitive workload: inclusive scan of 2^26 int32 U[0,100] (blockDim 512) "
+                        "+ 256-bin atomic histogram of 2^27 u32 Zipf(1.1) keys (LDS sub-histograms)",
+            "scan_n": SCAN_N, "scan_block": SCAN_BLOCK, "scan_items": SCAN_ITEMS,
+            "hist_n": HIST_N, "hist_grid": HIST_GRID, "hist_block": HIST_BLOCK,
+            "bytes_per_step": step_bytes,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def extra_workloads(spmd, synth):
+    """Per-kernel figures of the other workloads (not part of the step)."""
+    import torch
+
+    res = {}
+    # block reduction: 2^20 int32, grid 4096, block 256, 1 KiB LDS
+    log("reduce 2^20")
+    n = 1 << 20
+    x = to_dev(synth.uniform_int32(synth.SEED_REDUCE, n, -1000, 1000))
+    p = torch.empty(4096, dtype=torch.int32, device="cuda")
+    o = torch.empty(1, dtype=torch.int32, device="cuda")
+    wsr = spmd.ops.workspace(spmd.REDUCE_I32, 4096, 256, n)
+    ms = measure(lambda: spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr), 50)
+    b = 4 * n + 4 * 4096 + 4
+    res["reduce_i32 2^20 g4096 b256"] = {"us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1),
+                                        "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del x
+    # the same class where HBM, not launch latency, decides: 2^28 (1 GiB) and 2^30 (4 GiB)
+    for lg in (28, 30):
+        n = 1 << lg
+        log(f"reduce 2^{lg}")
+        x = torch.ones(n, dtype=torch.int32, device="cuda")
+        ms = measure(lambda: spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr), 10)
+        assert int(o.cpu()[0]) == n % 2**32 - (2**32 if n % 2**32 >= 2**31 else 0)
+        b = 4 * n + 4 * 4096 + 4
+        res[f"reduce_i32 2^{lg} g4096 b256"] = {"us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1),
+                                              "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        del x
+        torch.cuda.empty_cache()
+    # Jacobi 8192^2, 100 sweeps
+    nn, sweeps = 8192, 100
+    u = to_dev(synth.uniform_f32(synth.SEED_JACOBI, nn * nn).reshape(nn, nn))
+    a, bb = u.clone(), torch.empty_like(u)
+    for blk, cells in (((16, 16), 1), ((64, 4), 4)):
+        log(f"jacobi {blk} x{cells}")
+
+        def run():
+            src, dst = a, bb
+            for _ in range(sweeps):
+                spmd.ops.jacobi5_f32(src, dst, blk, cells)
+                src, dst = dst, src
+
+        ms = measure(run, 3, warmup=1) / sweeps
+        byt = 8 * nn * nn
+        res[f"jacobi5_f32 8192^2 block{blk[0]}x{blk[1]} c{cells} (per sweep, 100 sweeps)"] = {
+            "us": round(ms * 1e3, 2), "GB/s": round(byt / ms / 1e6, 1),
+            "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del u, a, bb
+    # GEMM 4096^3 fp32
+    n = 4096
+    A = to_dev(synth.normal_f32(synth.SEED_GEMM, n * n).reshape(n, n))
+    B = to_dev(synth.normal_f32(synth.SEED_GEMM + 1, n * n).reshape(n, n))
+    C = torch.empty_like(A)
+    for tile in (64, 128):
+        log(f"gemm tile {tile}")
+        ms = measure(lambda: spmd.ops.gemm_f32(A, B, C, tile), 10)
+        tf = 2 * n**3 / (ms * 1e-3) / 1e12
+        res[f"gemm_f32 4096^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
+                                              "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
+    spmd.sync()
+    return res
+
+
+def cpu_baseline(xs_h, ks_h, step_bytes):
+    """The oracle executor (thread-pool runtime of the paper, average
+    coarse-grained fetching) on the same step: scan then histogram."""
+    import oracle
+
+    pool = min(16, os.cpu_count() or 1)
+    log(f"cpu oracle, pool {pool}")
+    oracle.scan_i32(xs_h[:4096], SCAN_BLOCK, SCAN_ITEMS, pool=pool)  # start the pool
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.scan_i32(xs_h, SCAN_BLOCK, SCAN_ITEMS, pool=pool)
+        oracle.hist256_u32(ks_h, HIST_GRID, HIST_BLOCK, pool=pool)
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[1]
+    return {"value": round(step_bytes / t / 1e9, 3), "unit": "GB/s", "cores": pool, "kind": "oracle",
+            "sample": "the full step (scan 2^26 + hist 2^27) on the oracle's thread-pool executor, "
+                      f"median of 3 runs, {t:.2f} s each"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/* spmd.h -- C ABI of the MI355X (gfx950) SPMD kernel-grid executor.
+ *
+ * The library runs a fixed set of SPMD kernel classes, written by hand in HIP
+ * for gfx950, with the launch semantics of a CUDA grid: thread blocks whose
+ * threads run in phases separated by barriers, per-block shared memory (LDS),
+ * 32-lane warp shuffle/vote operations (kept on half-wavefronts of the
+ * 64-lane hardware wave) and atomics.  Blocks are dispatched either one grid
+ * per launch (the hardware dispatcher hands out workgroups) or, for a batch
+ * of many launches, by persistent workgroups that fetch chunks of logical
+ * blocks from a device queue -- the GPU form of the paper's task queue with
+ * coarse-grained fetching (Section IV, Section IV-A).
+ *
+ * Conventions (all entry points):
+ *  - Every function is extern "C", takes plain pointers and sizes, and
+ *    returns an int status: SPMD_OK (0) or a negative SPMD_ERR_* code.
+ *    Validation errors are returned before anything is enqueued and leave no
+ *    state behind.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Launches are asynchronous with respect to the host, as in the paper's
+ *    runtime where the host continues after pushing a task (Section IV,
+ *    "Push task queue"); a host read of a result needs spmd_sync first (the
+ *    barrier the paper inserts between a launch and a dependent copy,
+ *    Section III-C1).
+ *  - Kernel arguments are packed the way the paper's host prologue packs
+ *    them (Section III-C2): `args[i]` points to the value of parameter i (a
+ *    device pointer variable for pointer parameters, a uint32_t for sizes).
+ *    The values are read and copied during the call; `args` and what it
+ *    points to may be reused as soon as the call returns.
+ *  - Every data pointer is a device pointer owned by the caller, which keeps
+ *    it alive until the work completes.  Scratch memory ("workspace") is
+ *    also the caller's: it is sized by spmd_workspace_size, must be
+ *    zero-filled once before its first use, and is left reusable by every
+ *    launch that completes.  Two launches in flight at the same time must
+ *    not share a workspace.
+ *  - The library owns only immutable state (dispatch tables, device
+ *    attributes) and one device error word per device, which kernels set on
+ *    an internal failure and spmd_sync reports and clears.
+ */
+#ifndef SPMD_H
+#define SPMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    uint32_t x, y, z;
+} spmd_dim3;
+
+/* ------------------------------------------------------------------------
+ * Status codes
+ * ---------------------------------------------------------------------- */
+enum {
+    SPMD_OK = 0,
+    SPMD_ERR_INVALID_KERNEL = -1, /* unknown kernel id                                   */
+    SPMD_ERR_INVALID_DIM = -2,    /* zero dimension, block product > 1024, grid product
+                                     >= 2^32, or a shape the class does not accept      */
+    SPMD_ERR_SHMEM = -3,          /* dynamic + static shared memory over the device or
+                                     class limit, or below what the class needs          */
+    SPMD_ERR_ARGS = -4,           /* null args / null pointer / size mismatch            */
+    SPMD_ERR_HIP = -5,            /* a HIP runtime call failed                           */
+    SPMD_ERR_DEVICE = -6,         /* a kernel set the device error word                  */
+    SPMD_ERR_TIMEOUT = -7,        /* spmd_sync_timeout ran out of time                   */
+    SPMD_ERR_WORKSPACE = -8       /* workspace missing, too small or misaligned          */
+};
+
+/* ------------------------------------------------------------------------
+ * Kernel classes.  For each: parameters (the order of args[]), launch-shape
+ * rules, and what is computed.  Integer classes compute in uint32 arithmetic
+ * (sums wrap modulo 2^32 and are returned as int32 bit patterns).
+ * ---------------------------------------------------------------------- */
+enum {
+    /* Block tree reduction, one partial per block, then the last block to
+     * finish sums the partials.
+     * args: const int32_t* x, int32_t* partials, int32_t* out, uint32_t n,
+     *       void* workspace (spmd_workspace_size bytes, 16-byte aligned)
+     * grid (G,1,1), block (B,1,1) with B a power of two in [64, 1024].
+     * Block b owns x[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G));
+     * partials[b] = sum of its elements, *out = sum of all n elements. */
+    SPMD_REDUCE_I32 = 1,
+
+    /* Inclusive prefix sum: y[i] = x[0] + ... + x[i] (mod 2^32), single
+     * pass with decoupled look-back across tiles.
+     * args: const int32_t* x, int32_t* y, uint32_t n, void* workspace
+     * grid (G,1,1), block (B,1,1), B in {64,128,256,512,1024}.  Block g
+     * (in the order blocks start) scans a tile of B*I consecutive elements,
+     * I = the smallest power of two >= ceil(n / (G*B)); I must be <= 32.
+     * x and y may not overlap. */
+    SPMD_SCAN_I32 = 2,
+
+    /* 256-bin histogram of keys & 255 with per-block LDS sub-histograms
+     * (LDS atomics) flushed to hist with global atomics.  hist is
+     * overwritten: the library clears it in stream order before counting.
+     * args: const uint32_t* keys, uint32_t* hist, uint32_t n
+     * grid (G,1,1), block (B,1,1), B a power of two in [64, 1024].  Block b
+     * counts keys[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G)). */
+    SPMD_HIST256_U32 = 3,
+
+    /* One sweep of the 5-point Laplace-Jacobi stencil on an ny x nx
+     * row-major fp32 grid: interior u'[i][j] = 0.25f*((u[i-1][j] +
+     * u[i+1][j]) + (u[i][j-1] + u[i][j+1])), each operation rounded to
+     * fp32 in that order; border cells copied.  Each block stages its tile
+     * and a one-cell halo in LDS, barrier, then computes.
+     * args: const float* u, float* u_next, uint32_t nx, uint32_t ny
+     * block (BX,BY,1) with (BX,BY) in {(16,16), (32,8), (64,4), (64,8),
+     * (128,2), (128,4), (256,1)}; grid (GX,GY,1) with GX*BX >= nx; each
+     * thread computes C cells down its column, C = the smallest power of
+     * two >= ceil(ny / (GY*BY)), C <= 16.  u and u_next may not overlap. */
+    SPMD_JACOBI5_F32 = 4,
+
+    /* C = A * B, fp32 row-major, fp32 accumulation on the matrix cores
+     * (v_mfma_f32_32x32x2f32), LDS-staged T x T output tiles.
+     * args: const float* A, const float* B, float* C, uint32_t M,
+     *       uint32_t N, uint32_t K
+     * block (256,1,1); grid (GX,GY,1); the tile edge T is the smallest of
+     * {64, 128} with GX*T >= N and GY*T >= M. */
+    SPMD_GEMM_F32 = 5,
+
+    /* Conformance of the 32-lane warp operations on half-wavefronts.
+     * args: const int32_t* val, const uint32_t* pred, int32_t* out
+     * grid (G,1,1), block (B,1,1), B a multiple of 32.  With T = G*B
+     * threads and case c in [0, SPMD_WARPTEST_NCASES):
+     *   out[c*T + t] = result of case c on thread t, where
+     *   c <  768: op = (shfl, shfl_up, shfl_down, shfl_xor)[c / 192],
+     *             width = 1 << ((c / 32) % 6), parameter = c % 32,
+     *             applied to val (runtime parameter);
+     *   c <  864: vote = (ballot, any, all)[(c - 768) / 32] over predicate
+     *             bit (c - 768) % 32 of pred;
+     *   c <  904: k = c - 864, op = (up, down, xor, shfl)[k / 10],
+     *             width = 32 >> ((k / 5) % 2), parameter 1 << (k % 5), with
+     *             parameter and width known at compile time.
+     * Semantics follow CUDA's documented shfl/vote behaviour for full
+     * masks: a lane reading outside its width segment keeps its own value
+     * (xor may read earlier segments). */
+    SPMD_WARPTEST = 6,
+
+    /* The paper's dynamic-shared-memory example (Section III, listing
+     * cuda_reverse): one block of n threads, s[t] = d[t]; barrier;
+     * d[t] = s[n-1-t].
+     * args: int32_t* d, uint32_t n
+     * grid (1,1,1), block (n,1,1), dyn_shmem >= 4*n. */
+    SPMD_REVERSE_I32 = 7
+};
+
+#define SPMD_NUM_KERNELS 7
+#define SPMD_WARPTEST_NCASES 904
+
+/* Launch one grid of kernel class `kernel_id` on `stream` (Section IV, "Push
+ * task queue": the launch records grid, block, dynamic shared memory and the
+ * packed arguments and returns without waiting).  `dyn_shmem` bytes of
+ * dynamic LDS are reserved per block in addition to the class's static LDS.
+ * Returns SPMD_OK once the work is enqueued. */
+int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args, void* stream);
+
+/* Bytes of workspace a launch of `kernel_id` with this grid and block needs
+ * for n elements (0 when the class needs none). */
+size_t spmd_workspace_size(int kernel_id, spmd_dim3 grid, spmd_dim3 block, uint64_t n);
+
+/* Wait for all work on `stream`, then read and clear this device's error
+ * word: SPMD_ERR_DEVICE if a kernel set it since the last sync (the paper's
+ * host waits on a condition variable until the queue drains, Section IV). */
+int spmd_sync(void* stream);
+
+/* spmd_sync with a bound: polls the stream until it is idle or `ms`
+ * milliseconds have passed (SPMD_ERR_TIMEOUT; the work keeps running). */
+int spmd_sync_timeout(void* stream, uint32_t ms);
+
+/* Parameter kinds of a class as a string, one character per args[] entry:
+ * 'p' device pointer, 'u' uint32_t.  NULL for an unknown id. */
+const char* spmd_kernel_signature(int kernel_id);
+
+/* Name of a class ("reduce_i32", ...), NULL for an unknown id. */
+const char* spmd_kernel_name(int kernel_id);
+
+/* Text for a status code. */
+const char* spmd_error_string(int code);
+
+/* Text of the last HIP error seen by this thread's last failing call. */
+const char* spmd_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPMD_H */

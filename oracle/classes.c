@@ -439,7 +439,7 @@ static int hs_count(ox_block *b, uint32_t t) {
     const hist_params *p = b->params;
     uint64_t lo = (uint64_t)b->bidx[0] * p->seg;
     uint64_t hi = lo + p->seg < p->n ? lo + p->seg : p->n;
-    for (uint64_t j = lo + t; j < hi; j += b->block[0]) ox_s_atomic_add32(b, 4ull * (ox_g_ld32(b, 0, j) & 255u), 1u);
+    for (uint64_t j = lo + t; j < hi; j += b->block[0]) ox_sh_atomic_add32(b, 4ull * (ox_g_ld32(b, 0, j) & 255u), 1u);
     return 0;
 }
 static int hs_flush(ox_block *b, uint32_t t) {

@@ -111,7 +111,7 @@ void ox_s_st32(ox_block *b, uint64_t off, uint32_t v) {
     memcpy(p, &v, 4);
     memset(b->shm_w + off, 1, 4);
 }
-uint32_t ox_s_atomic_add32(ox_block *b, uint64_t off, uint32_t v) {
+uint32_t ox_sh_atomic_add32(ox_block *b, uint64_t off, uint32_t v) {
     /* threads of one block run one at a time, so a read-modify-write is
      * already atomic with respect to the block */
     uint32_t old = ox_s_ld32(b, off);

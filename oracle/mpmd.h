@@ -120,7 +120,7 @@ void ox_g_stf(ox_block *b, int buf, uint64_t i, float v);
 
 uint32_t ox_s_ld32(ox_block *b, uint64_t byte_off);
 void ox_s_st32(ox_block *b, uint64_t byte_off, uint32_t v);
-uint32_t ox_s_atomic_add32(ox_block *b, uint64_t byte_off, uint32_t v);
+uint32_t ox_sh_atomic_add32(ox_block *b, uint64_t byte_off, uint32_t v);
 float ox_s_ldf(ox_block *b, uint64_t byte_off);
 void ox_s_stf(ox_block *b, uint64_t byte_off, float v);
 

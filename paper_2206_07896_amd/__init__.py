@@ -1,0 +1,169 @@
+"""MI355X (gfx950) SPMD kernel-grid executor -- Python binding.
+
+A thin ctypes layer over ``libspmd.so`` (C ABI in ``include/spmd.h``): it
+only marshals arguments (tensor -> device pointer, int -> uint32) and turns
+status codes into exceptions.  Every step of every kernel class runs in the
+library's HIP kernels; PyTorch provides device memory and streams.
+
+The library must have been built (``python -m paper_2206_07896_amd.build``);
+importing this package without it raises ImportError -- there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspmd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2206_07896_amd.build` "
+        "(hipcc, gfx950); this package has no non-HIP implementation")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SPMD_OK = 0
+ERRORS = {
+    -1: "INVALID_KERNEL",
+    -2: "INVALID_DIM",
+    -3: "SHMEM",
+    -4: "ARGS",
+    -5: "HIP",
+    -6: "DEVICE",
+    -7: "TIMEOUT",
+    -8: "WORKSPACE",
+}
+
+REDUCE_I32 = 1
+SCAN_I32 = 2
+HIST256_U32 = 3
+JACOBI5_F32 = 4
+GEMM_F32 = 5
+WARPTEST = 6
+REVERSE_I32 = 7
+NUM_KERNELS = 7
+WARPTEST_NCASES = 904
+KERNELS = {}
+
+
+class Dim3(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_uint32), ("y", ctypes.c_uint32), ("z", ctypes.c_uint32)]
+
+
+class SpmdError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        msg = _lib.spmd_error_string(code).decode()
+        if code == -5:
+            msg += f" ({_lib.spmd_last_hip_error().decode()})"
+        super().__init__(f"{where}: {ERRORS.get(code, code)}: {msg}" if where else msg)
+        self.code = code
+        self.kind = ERRORS.get(code, str(code))
+
+
+_P = ctypes.c_void_p
+_lib.spmd_launch.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P]
+_lib.spmd_launch.restype = ctypes.c_int
+_lib.spmd_workspace_size.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_uint64]
+_lib.spmd_workspace_size.restype = ctypes.c_size_t
+_lib.spmd_sync.argtypes = [_P]
+_lib.spmd_sync.restype = ctypes.c_int
+_lib.spmd_sync_timeout.argtypes = [_P, ctypes.c_uint32]
+_lib.spmd_sync_timeout.restype = ctypes.c_int
+_lib.spmd_kernel_signature.argtypes = [ctypes.c_int]
+_lib.spmd_kernel_signature.restype = ctypes.c_char_p
+_lib.spmd_kernel_name.argtypes = [ctypes.c_int]
+_lib.spmd_kernel_name.restype = ctypes.c_char_p
+_lib.spmd_error_string.argtypes = [ctypes.c_int]
+_lib.spmd_error_string.restype = ctypes.c_char_p
+_lib.spmd_last_hip_error.argtypes = []
+_lib.spmd_last_hip_error.restype = ctypes.c_char_p
+
+for _k in range(1, NUM_KERNELS + 1):
+    KERNELS[_lib.spmd_kernel_name(_k).decode()] = _k
+
+
+def lib():
+    """The loaded ctypes library (for tests of the C ABI itself)."""
+    return _lib
+
+
+def _dim3(d) -> Dim3:
+    if isinstance(d, int):
+        return Dim3(d, 1, 1)
+    d = tuple(d) + (1,) * (3 - len(d))
+    return Dim3(*d)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(v) -> int:
+    if v is None:
+        return 0
+    if isinstance(v, int):
+        return v
+    return v.data_ptr()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != SPMD_OK:
+        raise SpmdError(rc, where)
+
+
+def signature(kernel: int) -> str:
+    s = _lib.spmd_kernel_signature(kernel)
+    if s is None:
+        raise SpmdError(-1, "signature")
+    return s.decode()
+
+
+def pack_args(kernel: int, args):
+    """The host prologue of the paper's parameter packing: one heap object
+    per parameter, args[i] pointing at it.  Returns (void** array, keepalive)."""
+    sig = signature(kernel)
+    if len(args) != len(sig):
+        raise SpmdError(-4, f"kernel {kernel} takes {len(sig)} arguments, got {len(args)}")
+    objs = []
+    for kind, v in zip(sig, args):
+        if kind == "p":
+            objs.append(ctypes.c_void_p(_ptr(v)))
+        else:
+            objs.append(ctypes.c_uint32(int(v)))
+    arr = (ctypes.c_void_p * len(objs))(*[ctypes.cast(ctypes.pointer(o), ctypes.c_void_p) for o in objs])
+    return arr, objs
+
+
+def launch(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None) -> None:
+    """spmd_launch: enqueue one grid of class ``kernel`` (id or name)."""
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    arr, keep = pack_args(kid, list(args))
+    rc = _lib.spmd_launch(kid, _dim3(grid), _dim3(block), dyn_shmem,
+                          ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), _stream_handle(stream))
+    del keep
+    _check(rc, f"spmd_launch({_lib.spmd_kernel_name(kid).decode() if 1 <= kid <= NUM_KERNELS else kid})")
+
+
+def workspace_size(kernel, grid, block, n: int) -> int:
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    return int(_lib.spmd_workspace_size(kid, _dim3(grid), _dim3(block), n))
+
+
+def sync(stream=None) -> None:
+    _check(_lib.spmd_sync(_stream_handle(stream)), "spmd_sync")
+
+
+def sync_timeout(stream=None, ms: int = 10000) -> None:
+    _check(_lib.spmd_sync_timeout(_stream_handle(stream), ms), "spmd_sync_timeout")
+
+
+from . import ops  # noqa: E402,F401  (tensor-level helpers)

@@ -1,0 +1,72 @@
+// common.hpp -- internal glue shared by the runtime and the kernel-class
+// translation units: the launch context handed to a class launcher, the
+// kernel-side parameter unpacking (the paper's kernel prologue, Section
+// III-C2: parameter i is read from the object args[i] points to), and the
+// device error bits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "spmd.h"
+
+namespace spmd {
+
+// Bits of the per-device error word.
+enum : uint32_t {
+    ERRBIT_SPIN_LIMIT = 1u,   // a cross-block wait gave up (look-back, queue)
+    ERRBIT_BAD_DESC = 2u,     // a batch descriptor named an unknown class
+    ERRBIT_QUEUE = 4u,        // a batch chunk fell outside its instance
+};
+
+struct DevInfo {
+    int device;
+    int num_cus;
+    size_t max_shmem_per_block;
+    uint32_t* err_word;  // device address of this device's error word
+};
+
+struct LaunchCtx {
+    int kernel_id;
+    spmd_dim3 grid, block;
+    size_t dyn_shmem;
+    void** args;
+    hipStream_t stream;
+    const DevInfo* dev;
+};
+
+// Kernel prologue: parameter i of the packed argument object.
+template <typename T>
+inline T arg(void** args, int i) {
+    return *reinterpret_cast<T*>(args[i]);
+}
+
+inline bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+inline uint32_t next_pow2(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Segment of a block in the reduce and histogram classes: S = 4*ceil(n/(4G)).
+inline uint32_t segment_len(uint32_t n, uint32_t grid) {
+    return (uint32_t)(4ull * ((n + 4ull * grid - 1) / (4ull * grid)));
+}
+
+int hip_fail(hipError_t e);  // records the HIP error text, returns SPMD_ERR_HIP
+
+// Class launchers (one translation unit each).  They validate the
+// class-specific rules and enqueue the work.
+int launch_reduce_i32(const LaunchCtx& c);
+int launch_scan_i32(const LaunchCtx& c);
+int launch_hist256_u32(const LaunchCtx& c);
+int launch_jacobi5_f32(const LaunchCtx& c);
+int launch_gemm_f32(const LaunchCtx& c);
+int launch_warptest(const LaunchCtx& c);
+int launch_reverse_i32(const LaunchCtx& c);
+
+size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
+size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
+
+}  // namespace spmd

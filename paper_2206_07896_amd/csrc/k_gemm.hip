@@ -1,0 +1,41 @@
+// k_gemm.hip -- GEMM_F32 kernel and launcher.
+#include "cls_gemm.hpp"
+
+namespace spmd {
+
+template <int T>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                                                        float* __restrict__ C, uint32_t M, uint32_t N, uint32_t K,
+                                                        bool vecA, bool vecB) {
+    __shared__ GemmLds<T> L;
+    gemm_block<T>(A, B, C, M, N, K, blockIdx.x, blockIdx.y, vecA, vecB, L);
+}
+
+int launch_gemm_f32(const LaunchCtx& c) {
+    if (c.block.x != 256 || c.block.y != 1 || c.block.z != 1 || c.grid.z != 1) return SPMD_ERR_INVALID_DIM;
+    auto A = arg<const float*>(c.args, 0);
+    auto B = arg<const float*>(c.args, 1);
+    auto C = arg<float*>(c.args, 2);
+    auto M = arg<uint32_t>(c.args, 3);
+    auto N = arg<uint32_t>(c.args, 4);
+    auto K = arg<uint32_t>(c.args, 5);
+    if (!A || !B || !C || M == 0 || N == 0 || K == 0) return SPMD_ERR_ARGS;
+    int T = 0;
+    for (int t : {64, 128})
+        if ((uint64_t)c.grid.x * t >= N && (uint64_t)c.grid.y * t >= M) {
+            T = t;
+            break;
+        }
+    if (!T) return SPMD_ERR_INVALID_DIM;
+    const bool vecA = aligned(A, 16) && (K % 4 == 0);
+    const bool vecB = aligned(B, 16) && (N % 4 == 0);
+    dim3 g(c.grid.x, c.grid.y), b(256);
+    if (T == 64)
+        hipLaunchKernelGGL(gemm_f32_kernel<64>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+    else
+        hipLaunchKernelGGL(gemm_f32_kernel<128>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+}  // namespace spmd

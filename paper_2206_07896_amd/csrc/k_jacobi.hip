@@ -1,0 +1,53 @@
+// k_jacobi.hip -- JACOBI5_F32 kernel and launcher.
+#include "cls_jacobi.hpp"
+
+namespace spmd {
+
+template <int BX, int BY, int C>
+__global__ __launch_bounds__(BX* BY) void jacobi5_kernel(const float* __restrict__ u, float* __restrict__ v,
+                                                          uint32_t nx, uint32_t ny) {
+    __shared__ JacobiLds<BX, BY, C> L;
+    jacobi_block<BX, BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, L);
+}
+
+template <int BX, int BY>
+static void launch_c(uint32_t C, dim3 g, size_t dyn, hipStream_t s, const float* u, float* v, uint32_t nx,
+                     uint32_t ny) {
+    dim3 b(BX, BY);
+    switch (C) {
+    case 1: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 1>), g, b, dyn, s, u, v, nx, ny); break;
+    case 2: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 2>), g, b, dyn, s, u, v, nx, ny); break;
+    case 4: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 4>), g, b, dyn, s, u, v, nx, ny); break;
+    case 8: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 8>), g, b, dyn, s, u, v, nx, ny); break;
+    case 16: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 16>), g, b, dyn, s, u, v, nx, ny); break;
+    }
+}
+
+int launch_jacobi5_f32(const LaunchCtx& c) {
+    const uint32_t BX = c.block.x, BY = c.block.y;
+    if (c.block.z != 1 || c.grid.z != 1) return SPMD_ERR_INVALID_DIM;
+    auto u = arg<const float*>(c.args, 0);
+    auto v = arg<float*>(c.args, 1);
+    auto nx = arg<uint32_t>(c.args, 2);
+    auto ny = arg<uint32_t>(c.args, 3);
+    if (!u || !v || nx == 0 || ny == 0) return SPMD_ERR_ARGS;
+    if ((uint64_t)c.grid.x * BX < nx) return SPMD_ERR_INVALID_DIM;
+    const uint64_t rows = (uint64_t)c.grid.y * BY;
+    const uint64_t per = (ny + rows - 1) / rows;
+    const uint32_t C = next_pow2((uint32_t)per);
+    if (C > 16) return SPMD_ERR_INVALID_DIM;
+    dim3 g(c.grid.x, c.grid.y);
+    const size_t d = c.dyn_shmem;
+    if (BX == 16 && BY == 16) launch_c<16, 16>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 32 && BY == 8) launch_c<32, 8>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 64 && BY == 4) launch_c<64, 4>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 64 && BY == 8) launch_c<64, 8>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 128 && BY == 2) launch_c<128, 2>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 128 && BY == 4) launch_c<128, 4>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 256 && BY == 1) launch_c<256, 1>(C, g, d, c.stream, u, v, nx, ny);
+    else return SPMD_ERR_INVALID_DIM;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+}  // namespace spmd

@@ -1,0 +1,43 @@
+// k_reduce.hip -- REDUCE_I32 kernel and launcher.
+#include "cls_reduce.hpp"
+#include "common.hpp"
+
+namespace spmd {
+
+template <int B>
+__global__ __launch_bounds__(B) void reduce_i32_kernel(const int32_t* __restrict__ x, int32_t* partials,
+                                                        int32_t* out, uint32_t n, uint32_t seg, uint32_t* counter,
+                                                        bool vec) {
+    __shared__ ReduceLds<B> L;
+    reduce_block<B>(x, partials, out, n, seg, gridDim.x, blockIdx.x, counter, vec, L);
+}
+
+size_t ws_reduce_i32(spmd_dim3, spmd_dim3, uint64_t) { return 16; }
+
+int launch_reduce_i32(const LaunchCtx& c) {
+    const uint32_t B = c.block.x;
+    if (c.block.y != 1 || c.block.z != 1 || c.grid.y != 1 || c.grid.z != 1) return SPMD_ERR_INVALID_DIM;
+    if (!is_pow2(B) || B < 64 || B > 1024) return SPMD_ERR_INVALID_DIM;
+    auto x = arg<const int32_t*>(c.args, 0);
+    auto partials = arg<int32_t*>(c.args, 1);
+    auto out = arg<int32_t*>(c.args, 2);
+    auto n = arg<uint32_t>(c.args, 3);
+    auto ws = arg<uint32_t*>(c.args, 4);
+    if ((!x && n) || !partials || !out) return SPMD_ERR_ARGS;
+    if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
+    const uint32_t G = c.grid.x;
+    const uint32_t seg = segment_len(n, G);
+    const bool vec = aligned(x, 16);
+    dim3 g(G), b(B);
+    switch (B) {
+    case 64: hipLaunchKernelGGL(reduce_i32_kernel<64>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    case 128: hipLaunchKernelGGL(reduce_i32_kernel<128>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    case 256: hipLaunchKernelGGL(reduce_i32_kernel<256>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    case 512: hipLaunchKernelGGL(reduce_i32_kernel<512>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    case 1024: hipLaunchKernelGGL(reduce_i32_kernel<1024>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+}  // namespace spmd

@@ -1,0 +1,268 @@
+"""Parity of the HIP kernel classes with the CPU oracle, through the C ABI.
+
+Integer classes must match bit for bit; the fp32 stencil must match the
+oracle's fp32 run bit for bit and stay within 1e-6 relative of the FP64
+run; the GEMM must stay within 1e-5*sqrt(K) max-normalised of the FP64
+product.  Sizes span several tiles plus ragged tails; the workload sizes
+are checked on sampled outputs or invariants.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def spmd():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2206_07896_amd as m
+
+    return m
+
+
+def dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+def host(t, dtype=None):
+    a = t.cpu().numpy()
+    return a.view(dtype) if dtype is not None else a
+
+
+# --------------------------------------------------------------------------
+# REVERSE (the paper's example) and warp conformance
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 31, 64, 100, 1024])
+def test_reverse(spmd, n):
+    say("reverse", n)
+    d = synth.uniform_int32(n, n, -(2**31), 2**31 - 1)
+    t = dev(d)
+    spmd.ops.reverse_i32(t)
+    spmd.sync()
+    assert np.array_equal(host(t), oracle.reverse_i32(d))
+
+
+@pytest.mark.parametrize("grid,block", [(2, 64), (1, 32), (3, 96), (1, 1024)])
+def test_warp_conformance(spmd, grid, block):
+    say("warptest", grid, block)
+    total = grid * block
+    val = synth.uniform_int32(0x57A, total, -(2**31), 2**31 - 1)
+    pred = synth.uniform_u32(0x57B, total)
+    pred[:32] = 0xFFFFFFFF
+    out = spmd.ops.warptest(dev(val), dev(pred), grid, block)
+    spmd.sync()
+    want = oracle.warptest(val, pred, grid, block)
+    got = host(out)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"first mismatches (case, thread): {bad[:5].tolist()} -> {[oracle.warptest_case(int(c)) for c, _ in bad[:5]]}"
+
+
+# --------------------------------------------------------------------------
+# REDUCE
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,grid,block", [(1, 1, 64), (1000, 3, 64), (12345, 37, 256), (1 << 16, 64, 1024),
+                                          (100003, 4096, 128), (1 << 20, 4096, 256)])
+def test_reduce(spmd, n, grid, block):
+    say("reduce", n, grid, block)
+    x = synth.uniform_int32(synth.SEED_REDUCE + n, n, -1000, 1000)
+    want_p, want_t = oracle.reduce_i32(x, grid, block)
+    xt = dev(x)
+    ws = spmd.ops.workspace(spmd.REDUCE_I32, grid, block, n)
+    for rep in range(3):  # the ticket counter re-arms itself
+        p, out = spmd.ops.reduce_i32(xt, grid, block, ws=ws)
+        spmd.sync()
+        assert int(host(out)[0]) == want_t, rep
+        assert np.array_equal(host(p), want_p), rep
+
+
+def test_reduce_wrapping_and_unaligned(spmd):
+    say("reduce wrap/unaligned")
+    n = 50001
+    x = synth.uniform_int32(99, n, -(2**31), 2**31 - 1)
+    xt = dev(x)
+    want_p, want_t = oracle.reduce_i32(x[1:], 13, 256)
+    p, out = spmd.ops.reduce_i32(xt[1:], 13, 256)  # 4-byte offset: scalar load path
+    spmd.sync()
+    assert int(host(out)[0]) == want_t
+    assert np.array_equal(host(p), want_p)
+
+
+# --------------------------------------------------------------------------
+# SCAN
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,block,items", [(1, 64, 1), (100, 64, 1), (5000, 64, 4), (8193, 128, 8), (70001, 512, 16),
+                                           (200000, 1024, 32), (123457, 256, 2)])
+def test_scan(spmd, n, block, items):
+    say("scan", n, block, items)
+    x = synth.uniform_int32(synth.SEED_SCAN + n, n, -(2**31), 2**31 - 1)
+    want = oracle.scan_i32(x, block=64, items=4)
+    xt = dev(x)
+    grid = spmd.ops.scan_grid(n, block, items)
+    ws = spmd.ops.workspace(spmd.SCAN_I32, grid, block, n)
+    for rep in range(3):  # epoch-tagged status words: no clearing between launches
+        y = spmd.ops.scan_i32(xt, block, items, ws=ws)
+        spmd.sync()
+        got = host(y)
+        assert np.array_equal(got, want), (rep, int(np.argmax(got != want)))
+
+
+def test_scan_workload_size(spmd):
+    n = 1 << 26
+    say("scan 2^26 block 512")
+    x = synth.uniform_int32(synth.SEED_SCAN, n, 0, 100)
+    y = spmd.ops.scan_i32(dev(x), 512, 16)
+    spmd.sync()
+    got = host(y).view(np.uint32)
+    xu = x.view(np.uint32)
+    assert got[0] == xu[0]
+    assert np.array_equal((got[1:] - got[:-1]).astype(np.uint32), xu[1:])
+    assert int(got[-1]) == int(x.astype(np.int64).sum()) % 2**32
+    m = 1 << 20  # a prefix of the scan is the scan of the prefix
+    assert np.array_equal(got[:m].view(np.int32), oracle.scan_i32(x[:m], 512, 16))
+
+
+# --------------------------------------------------------------------------
+# HIST256
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,grid,block", [(0, 4, 64), (1, 1, 64), (999, 3, 128), (100003, 64, 256),
+                                          (1 << 20, 1024, 512), (777777, 5, 1024)])
+def test_hist(spmd, n, grid, block):
+    say("hist", n, grid, block)
+    keys = synth.zipf_u32(synth.SEED_HIST + n, n) if n else np.zeros(0, np.uint32)
+    if n:
+        keys = keys ^ (synth.uniform_u32(3, n) & np.uint32(0xFFFFFF00))
+    want = oracle.hist256_u32(keys, grid, block)
+    kt = dev(keys) if n else dev(np.zeros(4, np.uint32))[:0]
+    for rep in range(2):  # the histogram is overwritten, not accumulated
+        h = spmd.ops.hist256_u32(kt, grid, block)
+        spmd.sync()
+        assert np.array_equal(host(h, np.uint32), want), rep
+
+
+def test_hist_workload_size(spmd):
+    n = 1 << 27
+    say("hist 2^27 zipf")
+    keys = synth.zipf_u32(synth.SEED_HIST, n)
+    h = spmd.ops.hist256_u32(dev(keys), 1024, 512)
+    spmd.sync()
+    got = host(h, np.uint32)
+    assert int(got.astype(np.int64).sum()) == n
+    assert np.array_equal(got, oracle.hist256_u32(keys, 1024, 512, pool=16))
+
+
+# --------------------------------------------------------------------------
+# JACOBI5
+# --------------------------------------------------------------------------
+
+SHAPES = [(16, 16), (32, 8), (64, 4), (64, 8), (128, 2), (128, 4), (256, 1)]
+
+
+@pytest.mark.parametrize("block", SHAPES)
+@pytest.mark.parametrize("cells", [1, 4])
+def test_jacobi_one_sweep(spmd, block, cells):
+    for (ny, nx) in [(33, 70), (130, 257), (3, 3)]:
+        say("jacobi", ny, nx, block, cells)
+        u = synth.uniform_f32(synth.SEED_JACOBI + nx, ny * nx).reshape(ny, nx)
+        want = oracle.jacobi5_f32(u, 16, 16)
+        got = host(spmd.ops.jacobi5_f32(dev(u), block=block, cells=cells))
+        spmd.sync()
+        assert np.array_equal(got, want)
+
+
+def test_jacobi_sweeps_bit_exact(spmd):
+    ny, nx = 300, 517
+    say("jacobi 25 sweeps", ny, nx)
+    u = synth.uniform_f32(5, ny * nx).reshape(ny, nx)
+    got = host(spmd.ops.jacobi5_sweeps(dev(u), 25, block=(64, 4), cells=4))
+    spmd.sync()
+    assert np.array_equal(got, oracle.jacobi5_f32_sweeps(u, 25))
+
+
+def test_jacobi_workload_size(spmd):
+    n, sweeps = 8192, 100
+    say("jacobi 8192^2 x 100, 16x16 blocks")
+    u = synth.uniform_f32(synth.SEED_JACOBI, n * n).reshape(n, n)
+    got = host(spmd.ops.jacobi5_sweeps(dev(u), sweeps, block=(16, 16), cells=1))
+    spmd.sync()
+    ref64 = oracle.jacobi5_f64(u, sweeps)
+    rel = np.abs(got.astype(np.float64) - ref64) / np.abs(ref64)
+    assert rel.max() <= 1e-6, rel.max()
+    assert np.array_equal(got, oracle.jacobi5_f32_sweeps(u, sweeps))
+
+
+# --------------------------------------------------------------------------
+# GEMM
+# --------------------------------------------------------------------------
+
+def _gemm_gate(C, c64, K):
+    return np.abs(C.astype(np.float64) - c64).max() / np.abs(c64).max() <= 1e-5 * np.sqrt(K)
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 64, 16), (65, 63, 17), (128, 96, 130), (3, 200, 5), (257, 130, 64),
+                                   (512, 512, 512)])
+def test_gemm_shapes(spmd, tile, M, N, K):
+    say("gemm", M, N, K, tile)
+    A = synth.normal_f32(M * 7 + K, M * K).reshape(M, K)
+    B = synth.normal_f32(N * 11 + K, K * N).reshape(K, N)
+    C = host(spmd.ops.gemm_f32(dev(A), dev(B), tile=tile))
+    spmd.sync()
+    c64 = oracle.gemm_f64(A, B)
+    assert _gemm_gate(C, c64, K)
+    gamma = K * 2.0**-24 / (1 - K * 2.0**-24)
+    bound = gamma * (np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64))
+    assert np.all(np.abs(C - c64) <= bound + 1e-30)
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_gemm_exact_cases(spmd, tile):
+    say("gemm exact", tile)
+    rng = np.random.default_rng(7)
+    M, N, K = 200, 136, 300
+    A = rng.integers(-2, 3, (M, K)).astype(np.float32)
+    B = rng.integers(-2, 3, (K, N)).astype(np.float32)
+    C = host(spmd.ops.gemm_f32(dev(A), dev(B), tile=tile))
+    assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+    A2 = synth.normal_f32(1, 100 * 77).reshape(100, 77)
+    C2 = host(spmd.ops.gemm_f32(dev(A2), dev(np.eye(77, dtype=np.float32)), tile=tile))
+    spmd.sync()
+    assert np.array_equal(C2, A2)
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_gemm_workload_size(spmd, tile):
+    n = 4096
+    say("gemm 4096^3", tile)
+    A = synth.normal_f32(synth.SEED_GEMM, n * n).reshape(n, n)
+    B = synth.normal_f32(synth.SEED_GEMM + 1, n * n).reshape(n, n)
+    C = host(spmd.ops.gemm_f32(dev(A), dev(B), tile=tile))
+    spmd.sync()
+    rng = np.random.default_rng(3)
+    rows = rng.choice(n, 4, replace=False)
+    ii = np.concatenate([np.repeat(rows, n), rng.integers(0, n, 4096)]).astype(np.uint32)
+    jj = np.concatenate([np.tile(np.arange(n), 4), rng.integers(0, n, 4096)]).astype(np.uint32)
+    c64 = oracle.gemm_f64_entries(A, B, ii, jj)
+    d = np.abs(C[ii, jj].astype(np.float64) - c64)
+    assert d.max() / np.abs(c64).max() <= 1e-5 * np.sqrt(n)
