@@ -37,7 +37,7 @@ FP32_MFMA_PEAK_TFS = 157.3     # MI355X dense fp32 matrix
 SCAN_N = 1 << 26
 HIST_N = 1 << 27
 SCAN_BLOCK, SCAN_ITEMS = 512, 16
-HIST_GRID, HIST_BLOCK = 1024, 512
+HIST_GRID, HIST_BLOCK = 256, 1024
 
 
 def log(*a):
@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch queue")
+    ap.add_argument("--mixed-count", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -167,7 +169,7 @@ def main():
     if ms_scan >= ms_hist:
         dom = ("scan_i32_kernel<512,16>", scan_bytes, ms_scan, scan_gbs)
     else:
-        dom = ("hist256_kernel<512>", hist_bytes, ms_hist, hist_gbs)
+        dom = ("hist256_kernel<1024>", hist_bytes, ms_hist, hist_gbs)
     roofline = {
         "kernel": dom[0],
         "bound": "hbm",
@@ -183,13 +185,17 @@ def main():
     kernels = {
         "scan_i32 2^26 b512": {"us": round(ms_scan * 1e3, 2), "GB/s": round(scan_gbs, 1),
                                "frac_hbm": round(scan_gbs / HBM_PEAK_GBS, 4)},
-        "hist256_u32 2^27 zipf1.1 g1024 b512": {"us": round(ms_hist * 1e3, 2), "GB/s": round(hist_gbs, 1),
+        "hist256_u32 2^27 zipf1.1 g256 b1024": {"us": round(ms_hist * 1e3, 2), "GB/s": round(hist_gbs, 1),
                                                 "frac_hbm": round(hist_gbs / HBM_PEAK_GBS, 4)},
     }
     del xs, ks, ys
     torch.cuda.empty_cache()
     if not args.no_extra:
         kernels.update(extra_workloads(spmd, synth))
+
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_queue(spmd, args.mixed_count)
 
     cpu = None
     if not args.no_cpu:
@@ -218,6 +224,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "mixed_queue": mixed,
     }
     print(json.dumps(out), flush=True)
 
@@ -282,6 +289,60 @@ def extra_workloads(spmd, synth):
         res[f"gemm_f32 4096^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
                                               "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
     spmd.sync()
+    return res
+
+
+def mixed_queue(spmd, count, reps=10):
+    """Mixed launches: `count` instances (class uniform over reduce, scan,
+    hist, jacobi; n = round(2^U), U ~ U[10, 22]; blockDim uniform over
+    64..512) run as one persistent-queue batch replayed from a hipGraph,
+    against one launch per instance from a host loop.  Same schedule for
+    both (the instance's blockDim, 4 items per thread, average
+    coarse-grained fetching); outputs must agree bit for bit."""
+    import torch
+
+    from paper_2206_07896_amd import workload as W
+
+    log(f"mixed queue: {count} instances")
+    specs = W.mixed_specs(count)
+    data = W.MixedData(specs)
+    sched = W.as_launched_schedules(specs)
+    b = spmd.batch.Batch(data.items(), sched)
+    st = b.stats()
+    b.graph_launch()
+    spmd.sync()
+    ref = data.outputs.clone()
+    data.outputs.fill_(-1)
+    b.launch_each()
+    spmd.sync()
+    same = bool(torch.equal(ref, data.outputs))
+    del ref
+    t_graph = measure(b.graph_launch, reps, warmup=2)
+    t_eager = measure(b.launch, reps, warmup=1)
+    t_each = measure(b.launch_each, max(3, reps // 2), warmup=1)
+    spmd.sync()
+    gbytes = data.total_bytes / 1e9
+    res = {
+        "instances": count,
+        "logical_blocks": st["blocks"],
+        "chunks": st["chunks"],
+        "kernel_launches_persistent": st["persistent_launches"],
+        "kernel_launches_one_by_one": st["each_launches"],
+        "outputs_identical": same,
+        "ms_persistent_graph": round(t_graph, 3),
+        "ms_persistent_eager": round(t_eager, 3),
+        "ms_one_by_one": round(t_each, 3),
+        "launches_per_s_persistent_graph": round(count / (t_graph * 1e-3), 1),
+        "launches_per_s_one_by_one": round(count / (t_each * 1e-3), 1),
+        "speedup_vs_one_by_one": round(t_each / t_graph, 3),
+        "GB/s_persistent_graph": round(gbytes / (t_graph * 1e-3), 1),
+        "frac_hbm_persistent_graph": round(gbytes / (t_graph * 1e-3) / HBM_PEAK_GBS, 4),
+        "schedule": "blockDim as launched, 4 items/thread, average coarse-grained fetching ceil(blocks/pool)",
+    }
+    log(f"mixed: graph {t_graph:.2f} ms, eager {t_eager:.2f} ms, one-by-one {t_each:.2f} ms, same={same}")
+    b.close()
+    del data
+    torch.cuda.empty_cache()
     return res
 
 

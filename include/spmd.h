@@ -76,7 +76,8 @@ enum {
     /* Block tree reduction, one partial per block, then the last block to
      * finish sums the partials.
      * args: const int32_t* x, int32_t* partials, int32_t* out, uint32_t n,
-     *       void* workspace (spmd_workspace_size bytes, 16-byte aligned)
+     *       void* workspace (spmd_workspace_size bytes = 256 + 8G, 16-byte
+     *       aligned)
      * grid (G,1,1), block (B,1,1) with B a power of two in [64, 1024].
      * Block b owns x[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G));
      * partials[b] = sum of its elements, *out = sum of all n elements. */
@@ -105,8 +106,8 @@ enum {
      * fp32 in that order; border cells copied.  Each block stages its tile
      * and a one-cell halo in LDS, barrier, then computes.
      * args: const float* u, float* u_next, uint32_t nx, uint32_t ny
-     * block (BX,BY,1) with (BX,BY) in {(16,16), (32,8), (64,4), (64,8),
-     * (128,2), (128,4), (256,1)}; grid (GX,GY,1) with GX*BX >= nx; each
+     * block (BX,BY,1) with (BX,BY) in {(16,16), (32,8), (64,1), (64,2),
+     * (64,4), (64,8), (128,2), (128,4), (256,1)}; grid (GX,GY,1) with GX*BX >= nx; each
      * thread computes C cells down its column, C = the smallest power of
      * two >= ceil(ny / (GY*BY)), C <= 16.  u and u_next may not overlap. */
     SPMD_JACOBI5_F32 = 4,

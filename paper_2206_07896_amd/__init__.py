@@ -5,7 +5,7 @@ only marshals arguments (tensor -> device pointer, int -> uint32) and turns
 status codes into exceptions.  Every step of every kernel class runs in the
 library's HIP kernels; PyTorch provides device memory and streams.
 
-The library must have been built (``python -m paper_2206_07896_amd.build``);
+The library must have been built (``python paper_2206_07896_amd/build.py``);
 importing this package without it raises ImportError -- there is no
 fallback implementation.
 """
@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libspmd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2206_07896_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_2206_07896_amd/build.py` "
         "(hipcc, gfx950); this package has no non-HIP implementation")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -167,3 +167,4 @@ def sync_timeout(stream=None, ms: int = 10000) -> None:
 
 
 from . import ops  # noqa: E402,F401  (tensor-level helpers)
+from . import batch  # noqa: E402,F401  (persistent block queue, device inputs)

@@ -2,7 +2,7 @@
 
 Every translation unit is compiled with hipcc for gfx950 only, with packed
 fp32 instructions disabled, then linked into one shared library next to this
-file.  ``python -m paper_2206_07896_amd.build`` rebuilds it.
+file.  ``python paper_2206_07896_amd/build.py`` rebuilds it.
 """
 
 from __future__ import annotations

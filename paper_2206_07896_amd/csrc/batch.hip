@@ -1,0 +1,584 @@
+// batch.hip -- persistent workgroups draining a device block queue.
+//
+// Queue layout (all in the caller's workspace):
+//   run area    cleared by the prologue kernel on every run:
+//                 16 fetch cursors (one per (class, block size) group,
+//                 64 B apart),
+//                 then per-instance scratch (REDUCE: ticket on its own
+//                 line + one status word per block; SCAN: one status
+//                 word per tile), 256-byte aligned
+//   each area   scratch of the one-launch-per-instance baseline (cleared
+//               once at creation; those launches re-arm it themselves)
+//   descriptors one 64-byte BatchDesc per instance (immutable)
+//   chunk maps  per group, the instance of every chunk, in queue order
+//
+// A chunk is up to `bpf` consecutive logical blocks of one instance; the
+// chunks of a group are numbered instance by instance, blocks ascending,
+// so a scan's tiles are fetched in order (its look-back waits only for
+// tiles fetched earlier).  A persistent workgroup takes a chunk with one
+// relaxed atomic add on its group's cursor and requests the next chunk as
+// soon as it starts the current one, so the atomic's round trip overlaps
+// the block bodies.  It exits when the cursor passes the group's chunk
+// count, so every workgroup ends after finitely many fetches.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "cls_hist.hpp"
+#include "cls_jacobi.hpp"
+#include "cls_reduce.hpp"
+#include "cls_scan.hpp"
+#include "spmd_batch.h"
+
+namespace spmd {
+
+struct alignas(16) BatchDesc {
+    uint32_t cls;
+    uint32_t n;        // elements (JACOBI: nx)
+    uint32_t ny;       // JACOBI rows
+    uint32_t nblocks;  // logical blocks
+    uint32_t items;    // items per thread / cells per thread
+    uint32_t bpf;      // blocks per fetch
+    uint32_t chunk0;   // first chunk of this instance in its group
+    uint32_t aux;      // REDUCE/HIST: elements per block; JACOBI: blocks per row
+    uint64_t in, out;
+    uint64_t ws;       // run-area scratch of this instance
+    uint32_t vec;      // in/out 16-byte aligned
+    uint32_t pad;
+};
+static_assert(sizeof(BatchDesc) == 64, "descriptor is 64 bytes");
+
+// One queue per (class, block size): each persistent kernel then holds only
+// one class body, which keeps its register use -- and so the number of
+// resident workers -- at that class's own level.
+constexpr int NSIZES = 4, NCLS = 4, NGROUPS = NSIZES * NCLS;
+constexpr size_t RUN_HEADER = 64 * NGROUPS;  // one 64-byte cursor slot per group
+constexpr uint32_t SIZE_B[NSIZES] = {64, 128, 256, 512};
+constexpr int CLS_ID[NCLS] = {SPMD_REDUCE_I32, SPMD_SCAN_I32, SPMD_HIST256_U32, SPMD_JACOBI5_F32};
+
+template <int CLS, int B>
+struct BatchLdsOf;
+template <int B>
+struct BatchLdsOf<SPMD_REDUCE_I32, B> {
+    ReduceLds<B> r;
+};
+template <int B>
+struct BatchLdsOf<SPMD_SCAN_I32, B> {
+    ScanLds<B> s;
+};
+template <int B>
+struct BatchLdsOf<SPMD_HIST256_U32, B> {
+    HistLds<HIST_COPIES> h;
+};
+template <int B>
+struct BatchLdsOf<SPMD_JACOBI5_F32, B> {
+    union {
+        JacobiLds<64, B / 64, 1> j1;
+        JacobiLds<64, B / 64, 2> j2;
+        JacobiLds<64, B / 64, 4> j4;
+        JacobiLds<64, B / 64, 8> j8;
+    };
+};
+
+template <int CLS, int B>
+__device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b, BatchLdsOf<CLS, B>& L,
+                                                  uint32_t* err) {
+    const uint32_t t = threadIdx.x;
+    if constexpr (CLS == SPMD_REDUCE_I32) {
+        uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
+        uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + 256);
+        reduce_block<B>(reinterpret_cast<const int32_t*>(d.in), nullptr, reinterpret_cast<int32_t*>(d.out), d.n,
+                        d.aux, d.nblocks, b, ctl, status, 0u, err, d.vec != 0u, L.r);
+    } else if constexpr (CLS == SPMD_SCAN_I32) {
+        const int32_t* x = reinterpret_cast<const int32_t*>(d.in);
+        int32_t* y = reinterpret_cast<int32_t*>(d.out);
+        uint64_t* st = reinterpret_cast<uint64_t*>(d.ws);
+        const bool v = d.vec != 0u;
+        switch (d.items) {
+        case 1: scan_tile<B, 1>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        case 2: scan_tile<B, 2>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        case 4: scan_tile<B, 4>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        }
+    } else if constexpr (CLS == SPMD_HIST256_U32) {
+        const uint64_t lo = (uint64_t)b * d.aux;
+        const uint64_t hi = lo + d.aux < (uint64_t)d.n ? lo + d.aux : (uint64_t)d.n;
+        hist_block<B, HIST_COPIES>(reinterpret_cast<const uint32_t*>(d.in), reinterpret_cast<uint32_t*>(d.out), lo,
+                                   hi, d.vec != 0u, L.h);
+    } else {
+        const float* u = reinterpret_cast<const float*>(d.in);
+        float* v = reinterpret_cast<float*>(d.out);
+        const uint32_t bx = b % d.aux, by = b / d.aux;
+        const int tx = (int)(t & 63u), ty = (int)(t >> 6);
+        switch (d.items) {
+        case 1: jacobi_block<64, B / 64, 1>(u, v, d.n, d.ny, bx, by, tx, ty, L.j1); break;
+        case 2: jacobi_block<64, B / 64, 2>(u, v, d.n, d.ny, bx, by, tx, ty, L.j2); break;
+        case 4: jacobi_block<64, B / 64, 4>(u, v, d.n, d.ny, bx, by, tx, ty, L.j4); break;
+        default: jacobi_block<64, B / 64, 8>(u, v, d.n, d.ny, bx, by, tx, ty, L.j8); break;
+        }
+    }
+}
+
+template <int CLS, int B>
+__global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __restrict__ descs,
+                                                              const uint32_t* __restrict__ chunk_inst,
+                                                              uint32_t total_chunks, uint32_t* cursor,
+                                                              uint32_t* err) {
+    __shared__ BatchLdsOf<CLS, B> L;
+    __shared__ uint32_t s_next;
+    const uint32_t t = threadIdx.x;
+    if (t == 0) s_next = atomic_add_dev(cursor, 1u);
+    __syncthreads();
+    uint32_t c = __builtin_amdgcn_readfirstlane(s_next);
+    while (c < total_chunks) {
+        __syncthreads();  // every thread has read s_next
+        uint32_t nxt = 0;
+        if (t == 0) nxt = atomic_add_dev(cursor, 1u);  // next fetch in flight during this chunk
+        const BatchDesc d = descs[chunk_inst[c]];
+        const uint32_t first = (c - d.chunk0) * d.bpf;
+        const uint32_t last = min(first + d.bpf, d.nblocks);
+        if (t == 0 && (first >= last || d.cls != (uint32_t)CLS)) atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
+        if (d.cls != (uint32_t)CLS) break;
+        for (uint32_t b = first; b < last; ++b) {
+            run_logical_block<CLS, B>(d, b, L, err);
+            __syncthreads();  // the next logical block reuses the LDS
+        }
+        if (t == 0) s_next = nxt;
+        __syncthreads();
+        c = __builtin_amdgcn_readfirstlane(s_next);
+    }
+}
+
+// Clears the run area (16-byte words) and the histogram outputs.
+__global__ __launch_bounds__(256) void batch_prologue_kernel(u32x4* run, uint64_t run_words,
+                                                             uint32_t* const* hist_out, uint32_t nhist) {
+    if (blockIdx.x < nhist) {
+        hist_out[blockIdx.x][threadIdx.x] = 0u;
+        return;
+    }
+    const uint64_t stride = (uint64_t)(gridDim.x - nhist) * 256u;
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (uint64_t i = (uint64_t)(blockIdx.x - nhist) * 256u + threadIdx.x; i < run_words; i += stride) run[i] = z;
+}
+
+}  // namespace spmd
+
+using namespace spmd;
+
+struct spmd_batch {
+    int n = 0;
+    std::vector<spmd_batch_item> items;
+    std::vector<spmd_schedule> sched;
+    std::vector<uint64_t> blocks;  // logical blocks per instance
+    uint8_t* ws = nullptr;
+    size_t run_bytes = 0, each_off = 0, desc_off = 0, hist_off = 0;
+    size_t chunk_off[NGROUPS] = {};
+    uint32_t chunks[NGROUPS] = {};
+    uint32_t grid[NGROUPS] = {};
+    std::vector<size_t> each_ws;        // per instance: offset of its standalone workspace
+    std::vector<size_t> each_partials;  // per instance (REDUCE): offset of its partials
+    uint32_t nhist = 0;
+    uint64_t total_blocks = 0, total_chunks = 0;
+    uint32_t each_launches = 0;
+    const DevInfo* dev = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int size_index(uint32_t block) {
+    for (int g = 0; g < NSIZES; ++g)
+        if (SIZE_B[g] == block) return g;
+    return -1;
+}
+int class_index(int kernel_id) {
+    for (int c = 0; c < NCLS; ++c)
+        if (CLS_ID[c] == kernel_id) return c;
+    return -1;
+}
+int group_of(int kernel_id, uint32_t block) {
+    const int si = size_index(block), ci = class_index(kernel_id);
+    return (si < 0 || ci < 0) ? -1 : ci * NSIZES + si;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Logical blocks of an item under a schedule, 0 if the pair is invalid.
+uint64_t item_blocks(const spmd_batch_item& it, const spmd_schedule& s) {
+    if (group_of(it.kernel_id, s.block) < 0 || s.bpf == 0) return 0;
+    const uint64_t per = (uint64_t)s.block * s.items;
+    switch (it.kernel_id) {
+    case SPMD_REDUCE_I32:
+    case SPMD_SCAN_I32:
+    case SPMD_HIST256_U32: {
+        if (s.items != 1 && s.items != 2 && s.items != 4 && s.items != 8 && s.items != 16) return 0;
+        const uint64_t nb = cdiv(it.n, per);
+        return nb ? nb : 1;
+    }
+    case SPMD_JACOBI5_F32: {
+        if (s.items != 1 && s.items != 2 && s.items != 4 && s.items != 8) return 0;
+        if (it.n == 0 || it.ny == 0) return 0;
+        const uint64_t by = s.block / 64;
+        return cdiv(it.n, 64) * cdiv(it.ny, by * s.items);
+    }
+    default: return 0;
+    }
+}
+
+// Run-area scratch of an instance under the queue.
+size_t run_scratch(const spmd_batch_item& it, uint64_t nb) {
+    if (it.kernel_id == SPMD_REDUCE_I32) return align_up(256 + 8 * nb, 256);
+    if (it.kernel_id == SPMD_SCAN_I32) return align_up(8 * nb, 256);
+    return 0;
+}
+
+// Scratch of the one-launch baseline (the class's workspace, then REDUCE
+// partials), 256-byte aligned pieces.
+size_t each_ws_bytes(const spmd_batch_item& it, uint64_t nb) {
+    const spmd_dim3 g{(uint32_t)nb, 1, 1}, b{64, 1, 1};
+    if (it.kernel_id == SPMD_REDUCE_I32) return align_up(ws_reduce_i32(g, b, it.n), 256);
+    if (it.kernel_id == SPMD_SCAN_I32) return align_up(ws_scan_i32(g, b, it.n), 256);
+    return 0;
+}
+size_t each_scratch(const spmd_batch_item& it, uint64_t nb) {
+    size_t s = each_ws_bytes(it, nb);
+    if (it.kernel_id == SPMD_REDUCE_I32) s += align_up(4 * nb, 256);
+    return s;
+}
+
+struct Layout {
+    size_t run_bytes, each_off, each_bytes, desc_off, hist_off, chunk_off[NGROUPS], total;
+    uint32_t chunks[NGROUPS];
+    uint32_t nhist;
+};
+
+int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, int n, std::vector<uint64_t>& blocks,
+                Layout& L) {
+    if (n <= 0 || !items || !sched) return SPMD_ERR_ARGS;
+    blocks.assign(n, 0);
+    size_t run = RUN_HEADER, each = 0;
+    uint64_t ch[NGROUPS] = {};
+    uint32_t nhist = 0;
+    for (int i = 0; i < n; ++i) {
+        const auto& it = items[i];
+        const auto& s = sched[i];
+        if (it.kernel_id != SPMD_REDUCE_I32 && it.kernel_id != SPMD_SCAN_I32 && it.kernel_id != SPMD_HIST256_U32 &&
+            it.kernel_id != SPMD_JACOBI5_F32)
+            return SPMD_ERR_INVALID_KERNEL;
+        const uint64_t nb = item_blocks(it, s);
+        if (nb == 0) return SPMD_ERR_INVALID_DIM;
+        if (nb >= (1ull << 31)) return SPMD_ERR_INVALID_DIM;
+        if (!it.out || (!it.in && it.n)) return SPMD_ERR_ARGS;
+        if (it.kernel_id == SPMD_JACOBI5_F32 && it.in == it.out) return SPMD_ERR_ARGS;
+        blocks[i] = nb;
+        run += run_scratch(it, nb);
+        each += each_scratch(it, nb);
+        ch[group_of(it.kernel_id, s.block)] += cdiv(nb, s.bpf);
+        if (it.kernel_id == SPMD_HIST256_U32) ++nhist;
+    }
+    for (int g = 0; g < NGROUPS; ++g)
+        if (ch[g] >= (1ull << 32) - 1) return SPMD_ERR_INVALID_DIM;
+    L.run_bytes = align_up(run, 256);
+    L.each_off = L.run_bytes;
+    L.each_bytes = align_up(each, 256);
+    L.desc_off = L.each_off + L.each_bytes;
+    L.hist_off = align_up(L.desc_off + sizeof(BatchDesc) * (size_t)n, 256);
+    size_t off = align_up(L.hist_off + 8 * (size_t)nhist, 256);
+    for (int g = 0; g < NGROUPS; ++g) {
+        L.chunk_off[g] = off;
+        L.chunks[g] = (uint32_t)ch[g];
+        off = align_up(off + 4 * ch[g], 256);
+    }
+    L.total = off;
+    L.nhist = nhist;
+    return SPMD_OK;
+}
+
+template <int CLS, int B>
+int occupancy(int* nb) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, batch_persistent_kernel<CLS, B>, B, 0);
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+template <int CLS>
+int occupancy_b(uint32_t block, int* nb) {
+    switch (block) {
+    case 64: return occupancy<CLS, 64>(nb);
+    case 128: return occupancy<CLS, 128>(nb);
+    case 256: return occupancy<CLS, 256>(nb);
+    case 512: return occupancy<CLS, 512>(nb);
+    }
+    return SPMD_ERR_INVALID_DIM;
+}
+
+int pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, const DevInfo* di, uint32_t* pool) {
+    int nb = 0, rc = SPMD_ERR_INVALID_KERNEL;
+    switch (kernel_id) {
+    case SPMD_REDUCE_I32: rc = occupancy_b<SPMD_REDUCE_I32>(block, &nb); break;
+    case SPMD_SCAN_I32: rc = occupancy_b<SPMD_SCAN_I32>(block, &nb); break;
+    case SPMD_HIST256_U32: rc = occupancy_b<SPMD_HIST256_U32>(block, &nb); break;
+    case SPMD_JACOBI5_F32: rc = occupancy_b<SPMD_JACOBI5_F32>(block, &nb); break;
+    }
+    if (rc) return rc;
+    if (workers_per_cu && (int)workers_per_cu < nb) nb = (int)workers_per_cu;
+    if (nb < 1) nb = 1;
+    *pool = (uint32_t)nb * (uint32_t)di->num_cus;
+    return SPMD_OK;
+}
+
+template <int CLS>
+void launch_group(uint32_t block, dim3 gr, hipStream_t s, const BatchDesc* descs, const uint32_t* cmap,
+                  uint32_t chunks, uint32_t* cursor, uint32_t* err) {
+    switch (block) {
+    case 64: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 64>), gr, dim3(64), 0, s, descs, cmap, chunks, cursor, err); break;
+    case 128: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 128>), gr, dim3(128), 0, s, descs, cmap, chunks, cursor, err); break;
+    case 256: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 256>), gr, dim3(256), 0, s, descs, cmap, chunks, cursor, err); break;
+    case 512: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 512>), gr, dim3(512), 0, s, descs, cmap, chunks, cursor, err); break;
+    }
+}
+
+int enqueue_run(spmd_batch* b, hipStream_t s) {
+    const uint64_t run_words = b->run_bytes / 16;
+    const uint32_t zero_blocks = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, cdiv(run_words, 256)));
+    hipLaunchKernelGGL(batch_prologue_kernel, dim3(b->nhist + zero_blocks), dim3(256), 0, s,
+                       reinterpret_cast<u32x4*>(b->ws), run_words,
+                       reinterpret_cast<uint32_t* const*>(b->ws + b->hist_off), b->nhist);
+    const BatchDesc* descs = reinterpret_cast<const BatchDesc*>(b->ws + b->desc_off);
+    uint32_t* err = b->dev->err_word;
+    for (int g = 0; g < NGROUPS; ++g) {
+        if (!b->chunks[g]) continue;
+        const uint32_t* cmap = reinterpret_cast<const uint32_t*>(b->ws + b->chunk_off[g]);
+        uint32_t* cursor = reinterpret_cast<uint32_t*>(b->ws + 64 * g);
+        const uint32_t block = SIZE_B[g % NSIZES];
+        const dim3 gr(b->grid[g]);
+        switch (CLS_ID[g / NSIZES]) {
+        case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t spmd_batch_item_blocks(const spmd_batch_item* item, const spmd_schedule* sched) {
+    if (!item || !sched) return 0;
+    return item_blocks(*item, *sched);
+}
+
+size_t spmd_batch_workspace_size(const spmd_batch_item* items, const spmd_schedule* sched, int n) {
+    std::vector<uint64_t> blocks;
+    Layout L;
+    if (plan_layout(items, sched, n, blocks, L) != SPMD_OK) return 0;
+    return L.total;
+}
+
+int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, int n, void* workspace,
+                      size_t ws_bytes, uint32_t workers_per_cu, spmd_batch** out) {
+    if (!out) return SPMD_ERR_ARGS;
+    *out = nullptr;
+    std::vector<uint64_t> blocks;
+    Layout L;
+    int rc = plan_layout(items, sched, n, blocks, L);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace % 256) || ws_bytes < L.total) return SPMD_ERR_WORKSPACE;
+    const DevInfo* di = nullptr;
+    if ((rc = runtime_dev(&di))) return rc;
+
+    auto* b = new spmd_batch();
+    b->n = n;
+    b->items.assign(items, items + n);
+    b->sched.assign(sched, sched + n);
+    b->blocks = blocks;
+    b->ws = static_cast<uint8_t*>(workspace);
+    b->run_bytes = L.run_bytes;
+    b->each_off = L.each_off;
+    b->desc_off = L.desc_off;
+    b->hist_off = L.hist_off;
+    b->nhist = L.nhist;
+    b->dev = di;
+    for (int g = 0; g < NGROUPS; ++g) {
+        b->chunk_off[g] = L.chunk_off[g];
+        b->chunks[g] = L.chunks[g];
+    }
+
+    // descriptors, chunk maps, histogram list, baseline scratch offsets
+    std::vector<BatchDesc> descs(n);
+    std::vector<std::vector<uint32_t>> cmap(NGROUPS);
+    for (int g = 0; g < NGROUPS; ++g) cmap[g].reserve(L.chunks[g]);
+    std::vector<uint64_t> hist_ptrs;
+    size_t run = RUN_HEADER, each = L.each_off;
+    b->each_ws.assign(n, 0);
+    b->each_partials.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const auto& it = items[i];
+        const auto& s = sched[i];
+        const int g = group_of(it.kernel_id, s.block);
+        BatchDesc& d = descs[i];
+        memset(&d, 0, sizeof d);
+        d.cls = (uint32_t)it.kernel_id;
+        d.n = it.n;
+        d.ny = it.ny;
+        d.nblocks = (uint32_t)blocks[i];
+        d.items = s.items;
+        d.bpf = s.bpf;
+        d.chunk0 = (uint32_t)cmap[g].size();
+        d.in = (uint64_t)(uintptr_t)it.in;
+        d.out = (uint64_t)(uintptr_t)it.out;
+        d.ws = (uint64_t)(uintptr_t)(b->ws + run);
+        const bool va = ((uintptr_t)it.in % 16) == 0;
+        const bool vb = ((uintptr_t)it.out % 16) == 0;
+        switch (it.kernel_id) {
+        case SPMD_REDUCE_I32:
+        case SPMD_HIST256_U32: d.aux = s.block * s.items; d.vec = va; break;
+        case SPMD_SCAN_I32: d.vec = va && vb; break;
+        case SPMD_JACOBI5_F32: d.aux = (uint32_t)cdiv(it.n, 64); break;
+        }
+        if (it.kernel_id == SPMD_HIST256_U32) hist_ptrs.push_back((uint64_t)(uintptr_t)it.out);
+        const uint64_t nch = cdiv(blocks[i], s.bpf);
+        for (uint64_t k = 0; k < nch; ++k) cmap[g].push_back((uint32_t)i);
+        run += run_scratch(it, blocks[i]);
+        if (it.kernel_id == SPMD_REDUCE_I32) {
+            b->each_ws[i] = each;
+            b->each_partials[i] = each + each_ws_bytes(it, blocks[i]);
+        } else if (it.kernel_id == SPMD_SCAN_I32) {
+            b->each_ws[i] = each;
+        }
+        each += each_scratch(it, blocks[i]);
+        b->total_blocks += blocks[i];
+        b->each_launches += it.kernel_id == SPMD_HIST256_U32 ? 2u : 1u;
+    }
+    hipError_t e = hipMemcpy(b->ws + L.desc_off, descs.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !hist_ptrs.empty())
+        e = hipMemcpy(b->ws + L.hist_off, hist_ptrs.data(), 8 * hist_ptrs.size(), hipMemcpyHostToDevice);
+    for (int g = 0; g < NGROUPS && e == hipSuccess; ++g)
+        if (!cmap[g].empty())
+            e = hipMemcpy(b->ws + L.chunk_off[g], cmap[g].data(), 4 * cmap[g].size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && L.each_bytes) e = hipMemset(b->ws + L.each_off, 0, L.each_bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e);
+    }
+    for (int g = 0; g < NGROUPS; ++g) {
+        b->total_chunks += b->chunks[g];
+        if (!b->chunks[g]) continue;
+        uint32_t pool = 0;
+        if ((rc = pool_size(CLS_ID[g / NSIZES], SIZE_B[g % NSIZES], workers_per_cu, di, &pool))) {
+            delete b;
+            return rc;
+        }
+        b->grid[g] = (uint32_t)std::min<uint64_t>(pool, b->chunks[g]);
+    }
+    *out = b;
+    return SPMD_OK;
+}
+
+int spmd_batch_launch(spmd_batch* b, void* stream) {
+    if (!b) return SPMD_ERR_ARGS;
+    return enqueue_run(b, static_cast<hipStream_t>(stream));
+}
+
+int spmd_batch_graph_launch(spmd_batch* b, void* stream) {
+    if (!b) return SPMD_ERR_ARGS;
+    hipError_t e;
+    if (!b->exec) {
+        if ((e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e);
+        if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return hip_fail(e);
+        int rc = enqueue_run(b, b->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(e);
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e);
+    }
+    e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+int spmd_batch_launch_each(spmd_batch* b, void* stream) {
+    if (!b) return SPMD_ERR_ARGS;
+    for (int i = 0; i < b->n; ++i) {
+        const auto& it = b->items[i];
+        const auto& s = b->sched[i];
+        const uint32_t nb = (uint32_t)b->blocks[i];
+        const void* in = it.in;
+        void* outp = it.out;
+        uint32_t n = it.n, ny = it.ny;
+        void* ws = b->ws + b->each_ws[i];
+        void* partials = b->ws + b->each_partials[i];
+        int rc = SPMD_OK;
+        switch (it.kernel_id) {
+        case SPMD_REDUCE_I32: {
+            void* args[] = {&in, &partials, &outp, &n, &ws};
+            rc = spmd_launch(SPMD_REDUCE_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+            break;
+        }
+        case SPMD_SCAN_I32: {
+            if (n == 0) break;
+            void* args[] = {&in, &outp, &n, &ws};
+            rc = spmd_launch(SPMD_SCAN_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+            break;
+        }
+        case SPMD_HIST256_U32: {
+            void* args[] = {&in, &outp, &n};
+            rc = spmd_launch(SPMD_HIST256_U32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+            break;
+        }
+        case SPMD_JACOBI5_F32: {
+            void* args[] = {&in, &outp, &n, &ny};
+            const uint32_t gx = (uint32_t)cdiv(n, 64);
+            rc = spmd_launch(SPMD_JACOBI5_F32, {gx, nb / gx, 1}, {64, s.block / 64, 1}, 0, args, stream);
+            break;
+        }
+        }
+        if (rc) return rc;
+    }
+    return SPMD_OK;
+}
+
+int spmd_batch_stats(const spmd_batch* b, uint64_t* blocks, uint64_t* chunks, uint32_t* persistent_launches,
+                     uint32_t* each_launches) {
+    if (!b) return SPMD_ERR_ARGS;
+    if (blocks) *blocks = b->total_blocks;
+    if (chunks) *chunks = b->total_chunks;
+    if (persistent_launches) {
+        uint32_t k = 1;
+        for (int g = 0; g < NGROUPS; ++g) k += b->chunks[g] ? 1u : 0u;  // prologue + one per group
+        *persistent_launches = k;
+    }
+    if (each_launches) *each_launches = b->each_launches;
+    return SPMD_OK;
+}
+
+int spmd_batch_pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, uint32_t* pool) {
+    if (!pool) return SPMD_ERR_ARGS;
+    if (class_index(kernel_id) < 0) return SPMD_ERR_INVALID_KERNEL;
+    if (size_index(block) < 0) return SPMD_ERR_INVALID_DIM;
+    const DevInfo* di = nullptr;
+    int rc = runtime_dev(&di);
+    if (rc) return rc;
+    return pool_size(kernel_id, block, workers_per_cu, di, pool);
+}
+
+int spmd_batch_destroy(spmd_batch* b) {
+    if (!b) return SPMD_ERR_ARGS;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    delete b;
+    return SPMD_OK;
+}
+
+}  // extern "C"

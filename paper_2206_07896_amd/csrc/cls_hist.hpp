@@ -19,6 +19,7 @@
 namespace spmd {
 
 constexpr int HIST_STRIDE = 257;
+constexpr int HIST_COPIES = 4;
 
 template <int COPIES>
 struct HistLds {

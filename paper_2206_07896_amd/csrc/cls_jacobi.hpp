@@ -2,11 +2,12 @@
 // 5-point Laplace-Jacobi stencil.
 //
 // A BX x BY block owns a tile of BX columns and BY*C rows (each thread
-// computes C cells down its column, C rows apart).  Phase 1 copies the tile
-// and a one-cell halo from HBM into LDS; barrier; phase 2 computes every
-// owned interior cell as 0.25f * ((N + S) + (W + E)) with each operation
-// rounded to fp32 in that order (no contraction), and copies border cells.
-// Cells outside the grid are neither loaded nor stored.
+// computes C cells down its column, BY rows apart).  Phase 1 copies the
+// tile and a one-cell halo from HBM into LDS; barrier; phase 2 computes
+// every owned interior cell as 0.25f * ((N + S) + (W + E)) with each
+// operation rounded to fp32 in that order (no contraction), and copies
+// border cells.  Cells outside the grid are never stored; halo cells
+// outside the grid are staged as zero and never read.
 #pragma once
 #include "common.hpp"
 
@@ -19,33 +20,49 @@ struct JacobiLds {
 
 template <int BX, int BY, int C>
 __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
-                                             uint32_t ny, uint32_t bx, uint32_t by, JacobiLds<BX, BY, C>& L) {
+                                             uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
+                                             JacobiLds<BX, BY, C>& L) {
 #pragma clang fp contract(off)
     constexpr int TY = BY * C;
-    constexpr int H = TY + 2, W = BX + 2;
-    const int tx = threadIdx.x, ty = threadIdx.y;
+    constexpr int H = TY + 2;
+    constexpr int NP = (H + BY - 1) / BY;  // row passes per thread
     const int64_t x0 = (int64_t)bx * BX, y0 = (int64_t)by * TY;
-    for (int r = ty; r < H; r += BY) {
+    const int64_t NX = nx, NY = ny;
+    // Every load of the tile and its halo is issued before the first LDS
+    // store, so each thread keeps NP (+NP halo) loads in flight.
+    const int64_t gxc = x0 + tx;                     // interior column of this thread
+    const int64_t gxh = tx == 0 ? x0 - 1 : x0 + BX;  // halo column (threads tx < 2)
+    const bool has_c = gxc < NX;
+    const bool has_h = tx < 2 && gxh >= 0 && gxh < NX;
+    float vc[NP], vh[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
         const int64_t gy = y0 - 1 + r;
-        if (gy < 0 || gy >= (int64_t)ny) continue;
-        const float* row = u + gy * (int64_t)nx;
-        for (int cc = tx; cc < W; cc += BX) {
-            const int64_t gx = x0 - 1 + cc;
-            if (gx >= 0 && gx < (int64_t)nx) L.t[r][cc] = row[gx];
+        const bool rowok = r < H && gy >= 0 && gy < NY;
+        vc[p] = (rowok && has_c) ? u[gy * NX + gxc] : 0.0f;
+        vh[p] = (rowok && has_h) ? u[gy * NX + gxh] : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
+        if (r < H) {
+            L.t[r][tx + 1] = vc[p];
+            if (tx < 2) L.t[r][tx == 0 ? 0 : BX + 1] = vh[p];
         }
     }
     __syncthreads();
-    const int64_t gx = x0 + tx;
-    if (gx >= (int64_t)nx) return;
-    const bool xborder = (gx == 0) || (gx == (int64_t)nx - 1);
+    const int64_t gx = gxc;
+    if (!has_c) return;
+    const bool xborder = (gx == 0) || (gx == NX - 1);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         const int r = ty + k * BY;
         const int64_t gy = y0 + r;
-        if (gy >= (int64_t)ny) break;
+        if (gy >= NY) break;
         const float c = L.t[r + 1][tx + 1];
         float out;
-        if (xborder || gy == 0 || gy == (int64_t)ny - 1) {
+        if (xborder || gy == 0 || gy == NY - 1) {
             out = c;
         } else {
             const float ns = L.t[r][tx + 1] + L.t[r + 2][tx + 1];
@@ -53,7 +70,7 @@ __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float*
             const float sum = ns + we;
             out = 0.25f * sum;
         }
-        v[gy * (int64_t)nx + gx] = out;
+        v[gy * NX + gx] = out;
     }
 }
 

@@ -11,6 +11,7 @@
 // wave).  Integer addition modulo 2^32 is associative and commutative, so
 // any tree shape gives the same bits.
 #pragma once
+#include "common.hpp"
 #include "warp32.hpp"
 
 namespace spmd {
@@ -68,34 +69,67 @@ __device__ __forceinline__ uint32_t segment_sum(const int32_t* __restrict__ x, u
     return acc;
 }
 
-// One logical block `bid` of a G-block reduction.
+constexpr uint32_t REDUCE_SPIN_LIMIT = 1u << 22;
+
+// One logical block `bid` of a G-block reduction.  Cross-block state
+// (`ctl`, `status`): ctl[0] is the completion ticket, status[b] the partial
+// of block b as a tagged status word.  Thread 0 publishes the block's
+// partial (to `partials`, when given, and as a status word), then takes a
+// ticket; the block holding ticket G-1 reads the G status words (waiting,
+// boundedly, for any not yet visible), sums them, writes *out, clears the
+// status words and re-arms the ticket, so the next launch finds the state
+// as the first one did.  Returns true in the block that finished.
 template <int B>
-__device__ __forceinline__ void reduce_block(const int32_t* __restrict__ x, int32_t* partials, int32_t* out,
-                                             uint32_t n, uint32_t seg, uint32_t G, uint32_t bid,
-                                             uint32_t* counter, bool vec, ReduceLds<B>& L) {
+__device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int32_t* partials, int32_t* out,
+                                             uint32_t n, uint32_t seg, uint32_t G, uint32_t bid, uint32_t* ctl,
+                                             uint64_t* status, uint32_t tag, uint32_t* err, bool vec,
+                                             ReduceLds<B>& L) {
     const uint64_t lo = (uint64_t)bid * seg;
     const uint64_t hi = lo + seg < (uint64_t)n ? lo + seg : (uint64_t)n;
-    uint32_t tot = block_sum_t0<B>(segment_sum<B>(x, lo, hi, vec), L);
+    const uint32_t tot = block_sum_t0<B>(segment_sum<B>(x, lo, hi, vec), L);
     if (threadIdx.x == 0) {
-        partials[bid] = (int32_t)tot;
-        fence_dev();  // the partial is visible before the ticket is taken
-        uint32_t ticket = atomic_add_dev(counter, 1u);
-        L.last = (ticket == G - 1u) ? 1u : 0u;
+        if (partials) partials[bid] = (int32_t)tot;
+        status_put(status + bid, status_pack(tot, 1u, tag));
+        L.last = (atomic_add_dev(ctl, 1u) == G - 1u) ? 1u : 0u;
     }
     __syncthreads();
     const bool last = L.last != 0u;
     __syncthreads();
-    if (!last) return;
-    fence_dev();  // acquire the other blocks' partials
+    if (!last) return false;
+    // The G status words, eight independent loads in flight per thread;
+    // only words not yet visible are polled again.
     uint32_t acc = 0;
-    for (uint32_t j = threadIdx.x; j < G; j += B)
-        acc += __hip_atomic_load(reinterpret_cast<uint32_t*>(partials) + j, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t total = block_sum_t0<B>(acc, L);
+    for (uint32_t j0 = threadIdx.x; j0 < G; j0 += 8u * B) {
+        uint64_t w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t j = j0 + (uint32_t)q * B;
+            w[q] = j < G ? status_get(status + j) : status_pack(0u, 1u, tag);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t j = j0 + (uint32_t)q * B;
+            for (uint32_t spins = 0; status_flag(w[q], tag) == 0u; ++spins) {
+                if (spins >= REDUCE_SPIN_LIMIT) {
+                    atomicOr(err, ERRBIT_SPIN_LIMIT);
+                    w[q] = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                w[q] = status_get(status + j);
+            }
+            acc += (uint32_t)(w[q] >> 32);
+        }
+    }
+    const uint32_t total = block_sum_t0<B>(acc, L);
+    // Every other block has published and returned: clear the status words
+    // and re-arm the ticket for the next launch.
+    for (uint32_t j = threadIdx.x; j < G; j += B) status_put(status + j, 0ull);
     if (threadIdx.x == 0) {
         *out = (int32_t)total;
-        store_release_dev(counter, 0u);  // re-arm for the next launch
+        put_dev(ctl, 0u);
     }
+    return true;
 }
 
 }  // namespace spmd

@@ -17,10 +17,7 @@
 // and the waits end.  Each wait is still bounded: past the spin limit the
 // tile flags the device error word and stops waiting.
 //
-// A status word is (value << 32) | (tag << 2) | flag with flag 1 = aggregate
-// and 2 = inclusive prefix; a word whose 30-bit tag differs from the
-// launch's tag counts as not yet written, so status arrays need no clearing
-// between launches that use different tags.
+// Status words (warp32.hpp) carry flag 1 = aggregate, 2 = inclusive prefix.
 #pragma once
 #include "common.hpp"
 #include "warp32.hpp"
@@ -36,39 +33,40 @@ struct ScanLds {
     uint32_t excl;
 };
 
-__device__ __forceinline__ uint64_t scan_pack(uint32_t v, uint32_t flag, uint32_t tag) {
-    return ((uint64_t)v << 32) | ((uint64_t)(tag & 0x3FFFFFFFu) << 2) | flag;
-}
-__device__ __forceinline__ uint32_t scan_flag(uint64_t s, uint32_t tag) {
-    return (((uint32_t)s >> 2) == (tag & 0x3FFFFFFFu)) ? ((uint32_t)s & 3u) : 0u;
-}
-__device__ __forceinline__ uint64_t status_get(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void status_put(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive carry of `tile`; called by the 64 lanes of wave 0.
+// Exclusive carry of `tile`, computed by wave 0 (the 64 lanes call it).
+// Polling is the costly part on gfx950: every status read is a device-
+// coherent access, and many tiles poll the same few lines.  So the wave
+// first polls only the immediate predecessor (one address for all lanes,
+// exponential back-off) until it has published; older predecessors have
+// almost always published by then.  It then reads 64 predecessors at a
+// time, waits (with back-off) for any lane still unwritten, keeps the words
+// up to the nearest inclusive prefix, and moves back 64 if there is none.
 __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t tile, uint32_t agg, uint32_t tag,
                                                   uint32_t* err) {
     const uint32_t lane = lane64();
     if (tile == 0) {
-        if (lane == 0) status_put(status, scan_pack(agg, SCAN_INCL, tag));
+        if (lane == 0) status_put(status, status_pack(agg, SCAN_INCL, tag));
         return 0;
     }
-    if (lane == 0) status_put(status + tile, scan_pack(agg, SCAN_AGG, tag));
+    if (lane == 0) status_put(status + tile, status_pack(agg, SCAN_AGG, tag));
+    uint32_t spins = 0, nap = 1;
+    while (status_flag(status_get(status + tile - 1), tag) == 0u) {
+        if (++spins >= LOOKBACK_SPIN_LIMIT) break;  // the window loop below reports it
+        backoff_sleep(nap);
+        nap = nap < 16u ? nap * 2u : 16u;
+    }
     uint32_t excl = 0;
     int64_t pos = (int64_t)tile - 1;
     for (;;) {
         const int64_t idx = pos - (int64_t)lane;
         uint64_t s = 0;
-        uint32_t f = SCAN_INCL;  // lanes before tile 0 read a zero prefix
-        uint32_t spins = 0;
+        uint32_t f = SCAN_INCL;  // before tile 0: a zero prefix
+        spins = 0;
+        nap = 1;
         for (;;) {
             if (idx >= 0) {
                 s = status_get(status + idx);
-                f = scan_flag(s, tag);
+                f = status_flag(s, tag);
             }
             if (__builtin_amdgcn_ballot_w64(f == 0u) == 0) break;
             if (++spins >= LOOKBACK_SPIN_LIMIT) {
@@ -79,7 +77,8 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
                 }
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
+            backoff_sleep(nap);
+            nap = nap < 16u ? nap * 2u : 16u;
         }
         const uint64_t incl = __builtin_amdgcn_ballot_w64(f == SCAN_INCL);
         const uint32_t val = (uint32_t)(s >> 32);
@@ -91,7 +90,7 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
         excl += wave_sum(val);
         pos -= 64;
     }
-    if (lane == 0) status_put(status + tile, scan_pack(excl + agg, SCAN_INCL, tag));
+    if (lane == 0) status_put(status + tile, status_pack(excl + agg, SCAN_INCL, tag));
     return excl;
 }
 

@@ -56,6 +56,9 @@ inline uint32_t segment_len(uint32_t n, uint32_t grid) {
 
 int hip_fail(hipError_t e);  // records the HIP error text, returns SPMD_ERR_HIP
 
+// State of the current device (created on first use with the device current).
+int runtime_dev(const DevInfo** out);
+
 // Class launchers (one translation unit each).  They validate the
 // class-specific rules and enqueue the work.
 int launch_reduce_i32(const LaunchCtx& c);

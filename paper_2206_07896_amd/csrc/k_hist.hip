@@ -5,8 +5,6 @@
 
 namespace spmd {
 
-constexpr int HIST_COPIES = 4;
-
 __global__ __launch_bounds__(256) void hist_clear_kernel(uint32_t* hist) { hist[threadIdx.x] = 0u; }
 
 template <int B>

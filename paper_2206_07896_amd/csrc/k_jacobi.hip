@@ -7,7 +7,7 @@ template <int BX, int BY, int C>
 __global__ __launch_bounds__(BX* BY) void jacobi5_kernel(const float* __restrict__ u, float* __restrict__ v,
                                                           uint32_t nx, uint32_t ny) {
     __shared__ JacobiLds<BX, BY, C> L;
-    jacobi_block<BX, BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, L);
+    jacobi_block<BX, BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, L);
 }
 
 template <int BX, int BY>
@@ -39,6 +39,8 @@ int launch_jacobi5_f32(const LaunchCtx& c) {
     dim3 g(c.grid.x, c.grid.y);
     const size_t d = c.dyn_shmem;
     if (BX == 16 && BY == 16) launch_c<16, 16>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 64 && BY == 1) launch_c<64, 1>(C, g, d, c.stream, u, v, nx, ny);
+    else if (BX == 64 && BY == 2) launch_c<64, 2>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 32 && BY == 8) launch_c<32, 8>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 64 && BY == 4) launch_c<64, 4>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 64 && BY == 8) launch_c<64, 8>(C, g, d, c.stream, u, v, nx, ny);

@@ -1,18 +1,25 @@
 // k_reduce.hip -- REDUCE_I32 kernel and launcher.
+//
+// Workspace: the u32 completion ticket alone on its cache line, then from
+// byte 256 one u64 status word per block (tag 0: the finishing block clears
+// them, so every launch starts from the zero-filled state).
 #include "cls_reduce.hpp"
 #include "common.hpp"
 
 namespace spmd {
 
+constexpr size_t REDUCE_WS_HEADER = 256;
+
 template <int B>
 __global__ __launch_bounds__(B) void reduce_i32_kernel(const int32_t* __restrict__ x, int32_t* partials,
-                                                        int32_t* out, uint32_t n, uint32_t seg, uint32_t* counter,
-                                                        bool vec) {
+                                                        int32_t* out, uint32_t n, uint32_t seg, uint32_t* ws,
+                                                        uint32_t* err, bool vec) {
     __shared__ ReduceLds<B> L;
-    reduce_block<B>(x, partials, out, n, seg, gridDim.x, blockIdx.x, counter, vec, L);
+    uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + REDUCE_WS_HEADER);
+    reduce_block<B>(x, partials, out, n, seg, gridDim.x, blockIdx.x, ws, status, 0u, err, vec, L);
 }
 
-size_t ws_reduce_i32(spmd_dim3, spmd_dim3, uint64_t) { return 16; }
+size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return REDUCE_WS_HEADER + 8ull * grid.x; }
 
 int launch_reduce_i32(const LaunchCtx& c) {
     const uint32_t B = c.block.x;
@@ -28,13 +35,14 @@ int launch_reduce_i32(const LaunchCtx& c) {
     const uint32_t G = c.grid.x;
     const uint32_t seg = segment_len(n, G);
     const bool vec = aligned(x, 16);
+    uint32_t* err = c.dev->err_word;
     dim3 g(G), b(B);
     switch (B) {
-    case 64: hipLaunchKernelGGL(reduce_i32_kernel<64>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
-    case 128: hipLaunchKernelGGL(reduce_i32_kernel<128>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
-    case 256: hipLaunchKernelGGL(reduce_i32_kernel<256>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
-    case 512: hipLaunchKernelGGL(reduce_i32_kernel<512>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
-    case 1024: hipLaunchKernelGGL(reduce_i32_kernel<1024>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, vec); break;
+    case 64: hipLaunchKernelGGL(reduce_i32_kernel<64>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, err, vec); break;
+    case 128: hipLaunchKernelGGL(reduce_i32_kernel<128>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, err, vec); break;
+    case 256: hipLaunchKernelGGL(reduce_i32_kernel<256>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, err, vec); break;
+    case 512: hipLaunchKernelGGL(reduce_i32_kernel<512>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, err, vec); break;
+    case 1024: hipLaunchKernelGGL(reduce_i32_kernel<1024>, g, b, c.dyn_shmem, c.stream, x, partials, out, n, seg, ws, err, vec); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);

@@ -1,37 +1,38 @@
 // k_scan.hip -- SCAN_I32 kernel and launcher.
 //
-// Workspace: u32 ticket, u32 done, u32 epoch, u32 pad, then one u64 status
-// word per tile.  Blocks take tile indices from the ticket in the order
-// they start; the last block to finish re-arms ticket and done and advances
-// the epoch, which is the tag of the next launch's status words.
+// Workspace: one 64-bit ticket word (epoch << 32 | count) alone on its
+// cache line, then from byte 256 one u64 status word per tile.  A block
+// takes its tile index from the ticket when it starts, so tiles start in
+// index order; the ticket's high half is the launch's epoch, the tag of its
+// status words.  The block that draws count G-1 -- every block of the
+// launch has drawn by then -- resets the count and advances the epoch.  One
+// atomic per tile, nothing to clear between launches.
 #include "cls_scan.hpp"
 
 namespace spmd {
+
+constexpr size_t SCAN_WS_HEADER = 256;
 
 template <int B, int I>
 __global__ __launch_bounds__(B) void scan_i32_kernel(const int32_t* __restrict__ x, int32_t* __restrict__ y,
                                                       uint32_t n, uint32_t* ws, uint32_t* err, bool vec) {
     __shared__ ScanLds<B> L;
     __shared__ uint32_t s_tile, s_tag;
-    uint64_t* status = reinterpret_cast<uint64_t*>(ws + 4);
+    uint64_t* ticket = reinterpret_cast<uint64_t*>(ws);
+    uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + SCAN_WS_HEADER);
     if (threadIdx.x == 0) {
-        s_tile = atomic_add_dev(ws + 0, 1u);
-        s_tag = __hip_atomic_load(ws + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tk = atomic_add_dev64(ticket, 1ull);
+        const uint32_t count = (uint32_t)tk, epoch = (uint32_t)(tk >> 32);
+        if (count == gridDim.x - 1u)
+            __hip_atomic_store(ticket, (uint64_t)(epoch + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_tile = count;
+        s_tag = epoch;
     }
     __syncthreads();
-    const uint32_t tile = s_tile, tag = s_tag;
-    scan_tile<B, I>(x, y, n, tile, status, tag, err, vec, L);
-    if (threadIdx.x == 0) {
-        const uint32_t d = atomic_add_dev(ws + 1, 1u);
-        if (d == gridDim.x - 1u) {
-            store_release_dev(ws + 0, 0u);
-            store_release_dev(ws + 1, 0u);
-            store_release_dev(ws + 2, tag + 1u);
-        }
-    }
+    scan_tile<B, I>(x, y, n, s_tile, status, s_tag, err, vec, L);
 }
 
-size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return 16 + 8ull * grid.x; }
+size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return SCAN_WS_HEADER + 8ull * grid.x; }
 
 template <int B>
 static void launch_b(uint32_t I, dim3 g, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t n,

@@ -62,8 +62,7 @@ int hip_fail(hipError_t e) {
     return SPMD_ERR_HIP;
 }
 
-// State of the current device, created on first use with the device current.
-static int current_dev(const DevInfo** out) {
+int runtime_dev(const DevInfo** out) {
     int d = 0;
     hipError_t e = hipGetDevice(&d);
     if (e != hipSuccess) return hip_fail(e);
@@ -117,7 +116,7 @@ int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem
     for (size_t i = 0; i < nargs; ++i)
         if (!args[i]) return SPMD_ERR_ARGS;
     const DevInfo* di = nullptr;
-    int rc = current_dev(&di);
+    int rc = runtime_dev(&di);
     if (rc) return rc;
     if (dyn_shmem > di->max_shmem_per_block) return SPMD_ERR_SHMEM;
     LaunchCtx c{kernel_id, grid, block, dyn_shmem, args, static_cast<hipStream_t>(stream), di};
@@ -131,7 +130,7 @@ size_t spmd_workspace_size(int kernel_id, spmd_dim3 grid, spmd_dim3 block, uint6
 
 int spmd_sync(void* stream) {
     const DevInfo* di = nullptr;
-    int rc = current_dev(&di);
+    int rc = runtime_dev(&di);
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e);
@@ -140,7 +139,7 @@ int spmd_sync(void* stream) {
 
 int spmd_sync_timeout(void* stream, uint32_t ms) {
     const DevInfo* di = nullptr;
-    int rc = current_dev(&di);
+    int rc = runtime_dev(&di);
     if (rc) return rc;
     const auto t0 = std::chrono::steady_clock::now();
     for (;;) {

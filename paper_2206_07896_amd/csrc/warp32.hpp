@@ -111,23 +111,45 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)s, 0) + (uint32_t)__builtin_amdgcn_readlane((int)s, 32);
 }
 
-// Device-scope atomics and ordered loads/stores used by cross-block
-// protocols (tickets, look-back status, queue cursors).
+// Cross-block protocols (tickets, look-back and partial-sum status words,
+// queue cursors) use only relaxed device-scope atomics.  On gfx950 these
+// are performed at the device coherence point (sc1) and need no cache
+// maintenance, whereas acquire/release at device scope writes back and
+// invalidates the whole L2 of the issuing XCD on every use.  No protocol
+// here needs such fences: every value a block hands to another block
+// travels inside the same 64-bit atomic word as its ready flag.
 __device__ __forceinline__ uint32_t atomic_add_dev(uint32_t* p, uint32_t v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint64_t load_acquire_dev(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t load_dev(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t load_acquire_dev(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void put_dev(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void store_release_dev(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t atomic_add_dev64(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void store_release_dev(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t status_get(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void fence_dev() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent"); }
+__device__ __forceinline__ void status_put(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A status word is (value << 32) | (tag << 2) | flag, flag in 1..3.  A word
+// whose 30-bit tag differs from the reader's tag reads as "not written", so
+// arrays of status words need no clearing between uses with different tags.
+__device__ __forceinline__ uint64_t status_pack(uint32_t v, uint32_t flag, uint32_t tag) {
+    return ((uint64_t)v << 32) | ((uint64_t)(tag & 0x3FFFFFFFu) << 2) | flag;
+}
+__device__ __forceinline__ uint32_t status_flag(uint64_t s, uint32_t tag) {
+    return (((uint32_t)s >> 2) == (tag & 0x3FFFFFFFu)) ? ((uint32_t)s & 3u) : 0u;
+}
+
+// Back-off between polls of a status word: `k` sleeps of 64 cycles.
+__device__ __forceinline__ void backoff_sleep(uint32_t k) {
+    for (uint32_t i = 0; i < k; ++i) __builtin_amdgcn_s_sleep(1);
+}
 
 }  // namespace spmd

@@ -60,7 +60,7 @@ def scan_i32(x: torch.Tensor, block: int = 512, items: int = 16, y=None, ws=None
     return y
 
 
-def hist256_u32(keys: torch.Tensor, grid: int = 1024, block: int = 512, hist=None, stream=None):
+def hist256_u32(keys: torch.Tensor, grid: int = 256, block: int = 1024, hist=None, stream=None):
     _check_dev(keys)
     if hist is None:
         hist = torch.empty(256, dtype=torch.int32, device=keys.device)

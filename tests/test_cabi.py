@@ -57,8 +57,8 @@ def test_error_strings(spmd):
 
 
 def test_workspace_sizes(spmd):
-    assert spmd.workspace_size(spmd.REDUCE_I32, 4096, 256, 1 << 20) == 16
-    assert spmd.workspace_size(spmd.SCAN_I32, 8192, 512, 1 << 26) == 16 + 8 * 8192
+    assert spmd.workspace_size(spmd.REDUCE_I32, 4096, 256, 1 << 20) == 256 + 8 * 4096
+    assert spmd.workspace_size(spmd.SCAN_I32, 8192, 512, 1 << 26) == 256 + 8 * 8192
     assert spmd.workspace_size(spmd.HIST256_U32, 10, 256, 100) == 0
     assert spmd.workspace_size(99, 1, 1, 1) == 0
 
@@ -96,3 +96,59 @@ def test_binding_arity_check(spmd):
     with pytest.raises(spmd.SpmdError) as e:
         spmd.pack_args(spmd.SCAN_I32, [0, 0])
     assert e.value.kind == "ARGS"
+
+
+# --------------------------------------------------------------------------
+# batch ABI (host-side parts)
+# --------------------------------------------------------------------------
+
+def test_batch_item_blocks(spmd):
+    ib = spmd.batch.item_blocks
+    R, S, H, J = spmd.REDUCE_I32, spmd.SCAN_I32, spmd.HIST256_U32, spmd.JACOBI5_F32
+    assert ib(R, 1000, 1, 64, 4) == 4          # ceil(1000 / 256)
+    assert ib(R, 0, 1, 64, 4) == 1             # an empty reduction still writes its total
+    assert ib(S, 1 << 20, 1, 512, 16) == 128
+    assert ib(H, (1 << 20) + 1, 1, 256, 16) == 257
+    assert ib(J, 100, 50, 256, 2) == 2 * 7     # 64-wide blocks of 4 rows x 2 cells
+    assert ib(J, 8192, 8192, 512, 8) == 128 * 128
+    for bad in [(S, 100, 1, 96, 4), (S, 100, 1, 1024, 4), (R, 100, 1, 64, 3), (J, 100, 1, 64, 16), (J, 0, 5, 64, 1),
+                (6, 100, 1, 64, 1)]:
+        assert ib(*bad) == 0, bad
+    assert ib(R, 100, 1, 64, 1, bpf=0) == 0
+
+
+def _items(spmd, specs):
+    import ctypes
+
+    B = spmd.batch
+    arr = (B.BatchItem * len(specs))()
+    sch = (B.Schedule * len(specs))()
+    for i, (kid, n, ny, s) in enumerate(specs):
+        arr[i] = B.BatchItem(kid, n, ny, 64, 0x1000, 0x2000)
+        sch[i] = B.Schedule(*s)
+    return arr, sch
+
+
+def test_batch_workspace_and_validation(spmd):
+    import ctypes
+
+    lib = spmd.lib()
+    R, S, H, J = spmd.REDUCE_I32, spmd.SCAN_I32, spmd.HIST256_U32, spmd.JACOBI5_F32
+    arr, sch = _items(spmd, [(R, 1000, 1, (64, 4, 1)), (S, 5000, 1, (128, 2, 3)), (H, 10, 1, (512, 16, 1)),
+                             (J, 30, 20, (256, 2, 2))])
+    size = lib.spmd_batch_workspace_size(arr, sch, 4)
+    # run area (cursors + reduce ticket/status + scan status) + baseline scratch + 4 descriptors + maps
+    assert size >= 256 + (256 + 8 * 4) + 8 * 20 + 4 * 64 and size % 256 == 0
+    h = ctypes.c_void_p()
+    # workspace checks come before any device work
+    assert lib.spmd_batch_create(arr, sch, 4, None, size, 0, ctypes.byref(h)) == -8
+    assert lib.spmd_batch_create(arr, sch, 4, 0x1000 + 16, size, 0, ctypes.byref(h)) == -8
+    assert lib.spmd_batch_create(arr, sch, 4, 0x100000, size - 1, 0, ctypes.byref(h)) == -8
+    bad_k, bad_s = _items(spmd, [(spmd.GEMM_F32, 10, 1, (64, 1, 1))])
+    assert lib.spmd_batch_workspace_size(bad_k, bad_s, 1) == 0
+    assert lib.spmd_batch_create(bad_k, bad_s, 1, 0x100000, 1 << 20, 0, ctypes.byref(h)) == -1
+    bad_k, bad_s = _items(spmd, [(S, 10, 1, (96, 1, 1))])
+    assert lib.spmd_batch_create(bad_k, bad_s, 1, 0x100000, 1 << 20, 0, ctypes.byref(h)) == -2
+    assert lib.spmd_batch_create(arr, sch, 0, 0x100000, 1 << 20, 0, ctypes.byref(h)) == -4
+    assert lib.spmd_batch_launch(None, None) == -4
+    assert lib.spmd_batch_destroy(None) == -4
