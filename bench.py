@@ -36,7 +36,7 @@ FP32_MFMA_PEAK_TFS = 157.3     # MI355X dense fp32 matrix
 
 SCAN_N = 1 << 26
 HIST_N = 1 << 27
-SCAN_BLOCK, SCAN_ITEMS = 512, 16
+SCAN_BLOCK, SCAN_ITEMS = 512, 32
 HIST_GRID, HIST_BLOCK = 256, 1024
 
 
@@ -76,6 +76,10 @@ class Timer:
     def mean_ms(self):
         return sum(s.elapsed_time(e) for s, e in self.pairs) / max(1, len(self.pairs))
 
+    def median_ms(self):
+        v = sorted(s.elapsed_time(e) for s, e in self.pairs)
+        return v[len(v) // 2] if v else 0.0
+
 
 def measure(fn, reps, warmup=2):
     import torch
@@ -89,7 +93,7 @@ def measure(fn, reps, warmup=2):
         fn()
         t.stop(s)
     torch.cuda.synchronize()
-    return t.mean_ms()
+    return t.median_ms()
 
 
 def main():
@@ -101,7 +105,11 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch queue")
     ap.add_argument("--mixed-count", type=int, default=10000)
+    ap.add_argument("--only-step", action="store_true",
+                    help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     args = ap.parse_args()
+    if args.only_step:
+        args.no_cpu = args.no_extra = args.no_mixed = True
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(each kernel class would shard over GPUs as described in DESIGN.md)", file=sys.stderr)
@@ -157,6 +165,15 @@ def main():
     h = hist.cpu().numpy().view(np.uint32)
     assert int(h.astype(np.int64).sum()) == HIST_N
 
+    if args.only_step:
+        # a copy of known size, for scaling hardware byte counters in profiler runs
+        src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     scan_bytes = 8 * SCAN_N
     hist_bytes = 4 * HIST_N + 1024
     step_bytes = scan_bytes + hist_bytes
@@ -167,9 +184,9 @@ def main():
     log(f"step {ms_per_step:.4f} ms  scan {ms_scan * 1e3:.1f} us {scan_gbs:.0f} GB/s  "
         f"hist {ms_hist * 1e3:.1f} us {hist_gbs:.0f} GB/s")
     if ms_scan >= ms_hist:
-        dom = ("scan_i32_kernel<512,16>", scan_bytes, ms_scan, scan_gbs)
+        dom = (f"scan_i32_kernel<{SCAN_BLOCK},{SCAN_ITEMS}>", scan_bytes, ms_scan, scan_gbs)
     else:
-        dom = ("hist256_kernel<1024>", hist_bytes, ms_hist, hist_gbs)
+        dom = (f"hist256_kernel<{HIST_BLOCK}>", hist_bytes, ms_hist, hist_gbs)
     roofline = {
         "kernel": dom[0],
         "bound": "hbm",
@@ -177,13 +194,14 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dom[3] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom[0]),
         "bytes_per_launch": dom[1],
         "avg_launch_us": round(dom[2] * 1e3, 2),
+        "timing": "HIP events on the launch stream around each launch over the timed steps",
     }
 
     kernels = {
-        "scan_i32 2^26 b512": {"us": round(ms_scan * 1e3, 2), "GB/s": round(scan_gbs, 1),
+        f"scan_i32 2^26 b{SCAN_BLOCK} i{SCAN_ITEMS}": {"us": round(ms_scan * 1e3, 2), "GB/s": round(scan_gbs, 1),
                                "frac_hbm": round(scan_gbs / HBM_PEAK_GBS, 4)},
         "hist256_u32 2^27 zipf1.1 g256 b1024": {"us": round(ms_hist * 1e3, 2), "GB/s": round(hist_gbs, 1),
                                                 "frac_hbm": round(hist_gbs / HBM_PEAK_GBS, 4)},
@@ -234,6 +252,13 @@ def extra_workloads(spmd, synth):
     import torch
 
     res = {}
+    # reference: a plain device copy of 256 MiB (read + write)
+    src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = measure(lambda: dst.copy_(src), 20)
+    res["reference: device copy 256 MiB (torch copy_)"] = {"us": round(ms * 1e3, 2),
+                                                          "GB/s": round(8 * (1 << 26) / ms / 1e6, 1)}
+    del src, dst
     # block reduction: 2^20 int32, grid 4096, block 256, 1 KiB LDS
     log("reduce 2^20")
     n = 1 << 20
@@ -344,6 +369,42 @@ def mixed_queue(spmd, count, reps=10):
     del data
     torch.cuda.empty_cache()
     return res
+
+
+def source_hash(paths):
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_SOURCES = {
+    "scan": ["paper_2206_07896_amd/csrc/k_scan.hip", "paper_2206_07896_amd/csrc/cls_scan.hpp",
+             "paper_2206_07896_amd/csrc/warp32.hpp"],
+    "hist": ["paper_2206_07896_amd/csrc/k_hist.hip", "paper_2206_07896_amd/csrc/cls_hist.hpp",
+             "paper_2206_07896_amd/csrc/warp32.hpp"],
+}
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading for a
+    copy of known size), or None when there is none or the kernel's sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    rec = data.get(kernel_name)
+    if not rec:
+        return None
+    cls = "scan" if kernel_name.startswith("scan") else "hist"
+    if rec.get("source_hash") != source_hash(TRAFFIC_SOURCES[cls]):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(xs_h, ks_h, step_bytes):

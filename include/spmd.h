@@ -76,7 +76,7 @@ enum {
     /* Block tree reduction, one partial per block, then the last block to
      * finish sums the partials.
      * args: const int32_t* x, int32_t* partials, int32_t* out, uint32_t n,
-     *       void* workspace (spmd_workspace_size bytes = 256 + 8G, 16-byte
+     *       void* workspace (spmd_workspace_size bytes = 8320 + 8G, 16-byte
      *       aligned)
      * grid (G,1,1), block (B,1,1) with B a power of two in [64, 1024].
      * Block b owns x[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G));

@@ -32,7 +32,9 @@ extern "C" {
  * fetched.  `block` threads per logical block (64, 128, 256 or 512);
  * `items` elements per thread (REDUCE, SCAN, HIST: 1, 2, 4, 8 or 16; JACOBI:
  * cells per thread down a column, 1, 2, 4 or 8, with blocks of 64 x
- * block/64 threads); `bpf` logical blocks per fetch (>= 1). */
+ * block/64 threads); `bpf` logical blocks per fetch (>= 1; a SCAN
+ * instance always fetches one tile at a time, since the tiles of one fetch
+ * run in sequence and its successor waits on the last of them). */
 typedef struct {
     uint32_t block;
     uint32_t items;

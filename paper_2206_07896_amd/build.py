@@ -63,7 +63,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(one, srcs))
     tmp = OUT + f".tmp{os.getpid()}"
-    cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [cc, "-shared", "-Wl,--no-undefined", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -65,7 +65,13 @@ struct BatchLdsOf<SPMD_REDUCE_I32, B> {
 };
 template <int B>
 struct BatchLdsOf<SPMD_SCAN_I32, B> {
-    ScanLds<B> s;
+    union {
+        ScanLds<B, 1> s1;
+        ScanLds<B, 2> s2;
+        ScanLds<B, 4> s4;
+        ScanLds<B, 8> s8;
+        ScanLds<B, 16> s16;
+    };
 };
 template <int B>
 struct BatchLdsOf<SPMD_HIST256_U32, B> {
@@ -87,7 +93,7 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
     const uint32_t t = threadIdx.x;
     if constexpr (CLS == SPMD_REDUCE_I32) {
         uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
-        uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + 256);
+        uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + REDUCE_CTL_BYTES);
         reduce_block<B>(reinterpret_cast<const int32_t*>(d.in), nullptr, reinterpret_cast<int32_t*>(d.out), d.n,
                         d.aux, d.nblocks, b, ctl, status, 0u, err, d.vec != 0u, L.r);
     } else if constexpr (CLS == SPMD_SCAN_I32) {
@@ -96,11 +102,11 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
         uint64_t* st = reinterpret_cast<uint64_t*>(d.ws);
         const bool v = d.vec != 0u;
         switch (d.items) {
-        case 1: scan_tile<B, 1>(x, y, d.n, b, st, 0u, err, v, L.s); break;
-        case 2: scan_tile<B, 2>(x, y, d.n, b, st, 0u, err, v, L.s); break;
-        case 4: scan_tile<B, 4>(x, y, d.n, b, st, 0u, err, v, L.s); break;
-        case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s); break;
-        default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s); break;
+        case 1: scan_tile<B, 1>(x, y, d.n, b, st, 0u, err, v, L.s1); break;
+        case 2: scan_tile<B, 2>(x, y, d.n, b, st, 0u, err, v, L.s2); break;
+        case 4: scan_tile<B, 4>(x, y, d.n, b, st, 0u, err, v, L.s4); break;
+        case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s8); break;
+        default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s16); break;
         }
     } else if constexpr (CLS == SPMD_HIST256_U32) {
         const uint64_t lo = (uint64_t)b * d.aux;
@@ -207,6 +213,14 @@ int group_of(int kernel_id, uint32_t block) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Blocks per fetch actually used.  A SCAN instance fetches one tile per
+// chunk: a worker runs the tiles of a chunk one after another, and the
+// first tile of the next chunk needs this chunk's last tile's aggregate,
+// so chunks of several tiles would run the instance serially.
+uint32_t effective_bpf(const spmd_batch_item& it, const spmd_schedule& s) {
+    return it.kernel_id == SPMD_SCAN_I32 ? 1u : s.bpf;
+}
+
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // Logical blocks of an item under a schedule, 0 if the pair is invalid.
@@ -233,7 +247,7 @@ uint64_t item_blocks(const spmd_batch_item& it, const spmd_schedule& s) {
 
 // Run-area scratch of an instance under the queue.
 size_t run_scratch(const spmd_batch_item& it, uint64_t nb) {
-    if (it.kernel_id == SPMD_REDUCE_I32) return align_up(256 + 8 * nb, 256);
+    if (it.kernel_id == SPMD_REDUCE_I32) return align_up(REDUCE_CTL_BYTES + 8 * nb, 256);
     if (it.kernel_id == SPMD_SCAN_I32) return align_up(8 * nb, 256);
     return 0;
 }
@@ -279,7 +293,7 @@ int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, int n,
         blocks[i] = nb;
         run += run_scratch(it, nb);
         each += each_scratch(it, nb);
-        ch[group_of(it.kernel_id, s.block)] += cdiv(nb, s.bpf);
+        ch[group_of(it.kernel_id, s.block)] += cdiv(nb, effective_bpf(it, s));
         if (it.kernel_id == SPMD_HIST256_U32) ++nhist;
     }
     for (int g = 0; g < NGROUPS; ++g)
@@ -432,7 +446,7 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
         d.ny = it.ny;
         d.nblocks = (uint32_t)blocks[i];
         d.items = s.items;
-        d.bpf = s.bpf;
+        d.bpf = effective_bpf(it, s);
         d.chunk0 = (uint32_t)cmap[g].size();
         d.in = (uint64_t)(uintptr_t)it.in;
         d.out = (uint64_t)(uintptr_t)it.out;
@@ -446,7 +460,7 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
         case SPMD_JACOBI5_F32: d.aux = (uint32_t)cdiv(it.n, 64); break;
         }
         if (it.kernel_id == SPMD_HIST256_U32) hist_ptrs.push_back((uint64_t)(uintptr_t)it.out);
-        const uint64_t nch = cdiv(blocks[i], s.bpf);
+        const uint64_t nch = cdiv(blocks[i], d.bpf);
         for (uint64_t k = 0; k < nch; ++k) cmap[g].push_back((uint32_t)i);
         run += run_scratch(it, blocks[i]);
         if (it.kernel_id == SPMD_REDUCE_I32) {

@@ -39,27 +39,42 @@ __device__ __forceinline__ uint32_t block_sum_t0(uint32_t v, ReduceLds<B>& L) {
     return tot;
 }
 
-// Thread t's share of x[lo, hi): element j with j - lo = t (mod B); four
-// 16-byte loads in flight per step when x + lo is 16-byte aligned.
+// Thread t's share of x[lo, hi): the segment is walked in rows of B
+// 16-byte chunks (one per thread), four rows in flight per step, starting
+// at a row that depends on the block: blocks whose segments lie a large
+// power of two apart then do not stream the same memory channels in
+// lockstep.  Integer sums do not depend on the order.
 template <int B>
-__device__ __forceinline__ uint32_t segment_sum(const int32_t* __restrict__ x, uint64_t lo, uint64_t hi, bool vec) {
+__device__ __forceinline__ uint32_t segment_sum(const int32_t* __restrict__ x, uint64_t lo, uint64_t hi, bool vec,
+                                                uint32_t bid) {
     const uint32_t t = threadIdx.x;
     uint32_t acc = 0;
     if (lo >= hi) return 0;
     if (vec) {
         const u32x4* xv = reinterpret_cast<const u32x4*>(x + lo);
         const uint64_t nv = (hi - lo) >> 2;
-        uint64_t k = t;
-        for (; k + 3 * B < nv; k += 4 * B) {
-            u32x4 a = __builtin_nontemporal_load(xv + k);
-            u32x4 b = __builtin_nontemporal_load(xv + k + B);
-            u32x4 c = __builtin_nontemporal_load(xv + k + 2 * B);
-            u32x4 d = __builtin_nontemporal_load(xv + k + 3 * B);
-            acc += (a.x + a.y) + (a.z + a.w) + (b.x + b.y) + (b.z + b.w);
-            acc += (c.x + c.y) + (c.z + c.w) + (d.x + d.y) + (d.z + d.w);
+        const uint64_t rows = nv / B;  // full rows
+        const uint64_t r0 = rows ? (bid * 7u) % rows : 0;
+        uint64_t r = 0;
+        for (; r + 4 <= rows; r += 4) {
+            u32x4 a[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint64_t row = r0 + r + q;
+                row = row >= rows ? row - rows : row;
+                a[q] = __builtin_nontemporal_load(xv + row * B + t);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc += (a[q].x + a[q].y) + (a[q].z + a[q].w);
         }
-        for (; k < nv; k += B) {
-            u32x4 a = __builtin_nontemporal_load(xv + k);
+        for (; r < rows; ++r) {
+            uint64_t row = r0 + r;
+            row = row >= rows ? row - rows : row;
+            const u32x4 a = __builtin_nontemporal_load(xv + row * B + t);
+            acc += (a.x + a.y) + (a.z + a.w);
+        }
+        for (uint64_t k = rows * B + t; k < nv; k += B) {
+            const u32x4 a = __builtin_nontemporal_load(xv + k);
             acc += (a.x + a.y) + (a.z + a.w);
         }
         for (uint64_t j = lo + (nv << 2) + t; j < hi; j += B) acc += (uint32_t)x[j];
@@ -70,15 +85,35 @@ __device__ __forceinline__ uint32_t segment_sum(const int32_t* __restrict__ x, u
 }
 
 constexpr uint32_t REDUCE_SPIN_LIMIT = 1u << 22;
+constexpr uint32_t REDUCE_SUBTICKETS = 64;   // first-level ticket counters
+constexpr uint32_t REDUCE_TICKET_STRIDE = 32;  // u32 words between counters (128 B)
+constexpr size_t REDUCE_CTL_BYTES = (REDUCE_SUBTICKETS + 1) * REDUCE_TICKET_STRIDE * 4;
+
+// Two-level completion ticket.  Counters on one address serialise at the
+// device coherence point, so block b counts on sub-counter b % 64 (each on
+// its own cache line); the block completing a sub-counter's group counts
+// once on the top counter, and the block completing the top counter is the
+// last of the grid.  Each completing block re-arms the counter it completed.
+__device__ __forceinline__ bool reduce_ticket_last(uint32_t* ctl, uint32_t G, uint32_t bid) {
+    const uint32_t sub = bid % REDUCE_SUBTICKETS;
+    const uint32_t members = (G - sub + REDUCE_SUBTICKETS - 1) / REDUCE_SUBTICKETS;
+    uint32_t* c1 = ctl + (1 + sub) * REDUCE_TICKET_STRIDE;
+    if (atomic_add_dev(c1, 1u) != members - 1u) return false;
+    put_dev(c1, 0u);
+    const uint32_t groups = G < REDUCE_SUBTICKETS ? G : REDUCE_SUBTICKETS;
+    if (atomic_add_dev(ctl, 1u) != groups - 1u) return false;
+    put_dev(ctl, 0u);
+    return true;
+}
 
 // One logical block `bid` of a G-block reduction.  Cross-block state
-// (`ctl`, `status`): ctl[0] is the completion ticket, status[b] the partial
-// of block b as a tagged status word.  Thread 0 publishes the block's
-// partial (to `partials`, when given, and as a status word), then takes a
-// ticket; the block holding ticket G-1 reads the G status words (waiting,
-// boundedly, for any not yet visible), sums them, writes *out, clears the
-// status words and re-arms the ticket, so the next launch finds the state
-// as the first one did.  Returns true in the block that finished.
+// (`ctl`, `status`): `ctl` holds the two-level completion ticket
+// (REDUCE_CTL_BYTES), status[b] the partial of block b as a tagged status
+// word.  Thread 0 publishes the block's partial (to `partials`, when given,
+// and as a status word), then takes a ticket; the last block reads the G
+// status words (waiting, boundedly, for any not yet visible), sums them,
+// writes *out and clears the status words, so the next launch finds the
+// state as the first one did.  Returns true in the block that finished.
 template <int B>
 __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int32_t* partials, int32_t* out,
                                              uint32_t n, uint32_t seg, uint32_t G, uint32_t bid, uint32_t* ctl,
@@ -86,11 +121,11 @@ __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int3
                                              ReduceLds<B>& L) {
     const uint64_t lo = (uint64_t)bid * seg;
     const uint64_t hi = lo + seg < (uint64_t)n ? lo + seg : (uint64_t)n;
-    const uint32_t tot = block_sum_t0<B>(segment_sum<B>(x, lo, hi, vec), L);
+    const uint32_t tot = block_sum_t0<B>(segment_sum<B>(x, lo, hi, vec, bid), L);
     if (threadIdx.x == 0) {
         if (partials) partials[bid] = (int32_t)tot;
         status_put(status + bid, status_pack(tot, 1u, tag));
-        L.last = (atomic_add_dev(ctl, 1u) == G - 1u) ? 1u : 0u;
+        L.last = reduce_ticket_last(ctl, G, bid) ? 1u : 0u;
     }
     __syncthreads();
     const bool last = L.last != 0u;
@@ -123,12 +158,9 @@ __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int3
     }
     const uint32_t total = block_sum_t0<B>(acc, L);
     // Every other block has published and returned: clear the status words
-    // and re-arm the ticket for the next launch.
+    // for the next launch.
     for (uint32_t j = threadIdx.x; j < G; j += B) status_put(status + j, 0ull);
-    if (threadIdx.x == 0) {
-        *out = (int32_t)total;
-        put_dev(ctl, 0u);
-    }
+    if (threadIdx.x == 0) *out = (int32_t)total;
     return true;
 }
 

@@ -27,11 +27,27 @@ namespace spmd {
 constexpr uint32_t SCAN_AGG = 1u, SCAN_INCL = 2u;
 constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 22;
 
-template <int B>
+template <int B, int I>
 struct ScanLds {
     uint32_t warp[B / 32];
     uint32_t excl;
+    // Tile staging for I >= 4: the tile travels between HBM and registers
+    // through LDS so that global loads and stores are fully coalesced
+    // (lane-consecutive 16-byte chunks) while each thread still owns I
+    // consecutive items.
+    alignas(16) uint32_t tile[I >= 4 ? B * I : 4];
 };
+
+// LDS slot of 16-byte chunk c of a staged tile with S chunks per thread:
+// c ^ ((c / S) mod 8).  It permutes chunks within aligned groups of eight,
+// so that both the striped pass (lanes take consecutive chunks) and the
+// blocked pass (lane t takes chunks t*S .. t*S+S-1) touch eight distinct
+// slots per eight lanes: no LDS bank conflicts either way.
+template <int S>
+__device__ __forceinline__ uint32_t stage_slot(uint32_t c) {
+    if constexpr (S >= 2) return c ^ ((c / S) & 7u);
+    else return c;
+}
 
 // Exclusive carry of `tile`, computed by wave 0 (the 64 lanes call it).
 // Polling is the costly part on gfx950: every status read is a device-
@@ -99,29 +115,38 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
 template <int B, int I>
 __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t* __restrict__ y, uint32_t n,
                                           uint32_t tile, uint64_t* status, uint32_t tag, uint32_t* err, bool vec,
-                                          ScanLds<B>& L) {
+                                          ScanLds<B, I>& L) {
     constexpr uint64_t T = (uint64_t)B * I;
     constexpr int NW = B / 32;
+    constexpr int S = I / 4;  // 16-byte chunks per thread
     const uint32_t t = threadIdx.x;
-    const uint64_t base = (uint64_t)tile * T + (uint64_t)t * I;
-    const bool full = base + I <= (uint64_t)n;
+    const uint64_t tbase = (uint64_t)tile * T;
+    const uint64_t base = tbase + (uint64_t)t * I;
+    // a full, aligned tile is staged through LDS; the rest is read directly
+    bool staged = false;
+    if constexpr (I >= 4) staged = vec && tbase + T <= (uint64_t)n;
     uint32_t v[I];
-    if constexpr (I % 4 == 0) {
-        if (vec && full) {
-            const u32x4* xv = reinterpret_cast<const u32x4*>(x + base);
+    if constexpr (I >= 4) {
+        if (staged) {
+            const u32x4* xv = reinterpret_cast<const u32x4*>(x + tbase);
+            u32x4 r[S];
 #pragma unroll
-            for (int q = 0; q < I / 4; ++q) {
-                u32x4 a = __builtin_nontemporal_load(xv + q);
-                v[4 * q] = a.x;
-                v[4 * q + 1] = a.y;
-                v[4 * q + 2] = a.z;
-                v[4 * q + 3] = a.w;
+            for (int q = 0; q < S; ++q) r[q] = __builtin_nontemporal_load(xv + q * B + t);
+            u32x4* st = reinterpret_cast<u32x4*>(L.tile);
+#pragma unroll
+            for (int q = 0; q < S; ++q) st[stage_slot<S>(q * B + t)] = r[q];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const u32x4 a = st[stage_slot<S>(t * S + j)];
+                v[4 * j] = a.x;
+                v[4 * j + 1] = a.y;
+                v[4 * j + 2] = a.z;
+                v[4 * j + 3] = a.w;
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
         }
-    } else {
+    }
+    if (!staged) {
 #pragma unroll
         for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
     }
@@ -145,18 +170,24 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
     }
     __syncthreads();
     const uint32_t pre = L.excl + wpre + (wincl - tot);
-    if constexpr (I % 4 == 0) {
-        if (vec && full) {
-            u32x4* yv = reinterpret_cast<u32x4*>(y + base);
+    if constexpr (I >= 4) {
+        if (staged) {
+            // each thread rewrites only the slots it read, then the tile
+            // leaves through LDS in lane-consecutive chunks
+            u32x4* st = reinterpret_cast<u32x4*>(L.tile);
 #pragma unroll
-            for (int q = 0; q < I / 4; ++q) {
+            for (int j = 0; j < S; ++j) {
                 u32x4 a;
-                a.x = pre + v[4 * q];
-                a.y = pre + v[4 * q + 1];
-                a.z = pre + v[4 * q + 2];
-                a.w = pre + v[4 * q + 3];
-                __builtin_nontemporal_store(a, yv + q);
+                a.x = pre + v[4 * j];
+                a.y = pre + v[4 * j + 1];
+                a.z = pre + v[4 * j + 2];
+                a.w = pre + v[4 * j + 3];
+                st[stage_slot<S>(t * S + j)] = a;
             }
+            __syncthreads();
+            u32x4* yv = reinterpret_cast<u32x4*>(y + tbase);
+#pragma unroll
+            for (int q = 0; q < S; ++q) __builtin_nontemporal_store(st[stage_slot<S>(q * B + t)], yv + q * B + t);
             return;
         }
     }

@@ -1,14 +1,15 @@
 // k_reduce.hip -- REDUCE_I32 kernel and launcher.
 //
-// Workspace: the u32 completion ticket alone on its cache line, then from
-// byte 256 one u64 status word per block (tag 0: the finishing block clears
-// them, so every launch starts from the zero-filled state).
+// Workspace: the two-level completion ticket (REDUCE_CTL_BYTES, counters
+// on separate cache lines), then one u64 status word per block (tag 0: the
+// finishing block clears them, so every launch starts from the zero-filled
+// state).
 #include "cls_reduce.hpp"
 #include "common.hpp"
 
 namespace spmd {
 
-constexpr size_t REDUCE_WS_HEADER = 256;
+constexpr size_t REDUCE_WS_HEADER = REDUCE_CTL_BYTES;
 
 template <int B>
 __global__ __launch_bounds__(B) void reduce_i32_kernel(const int32_t* __restrict__ x, int32_t* partials,

@@ -1,12 +1,13 @@
-// k_scan.hip -- SCAN_I32 kernel and launcher.
+// k_scan.hip -- SCAN_I32 kernels and launcher.
 //
-// Workspace: one 64-bit ticket word (epoch << 32 | count) alone on its
-// cache line, then from byte 256 one u64 status word per tile.  A block
-// takes its tile index from the ticket when it starts, so tiles start in
-// index order; the ticket's high half is the launch's epoch, the tag of its
-// status words.  The block that draws count G-1 -- every block of the
-// launch has drawn by then -- resets the count and advances the epoch.  One
-// atomic per tile, nothing to clear between launches.
+// Workspace (zero-filled once): a 64-bit ticket word (epoch << 32 | count)
+// alone on its cache line, then from byte 256 one u64 status word per
+// tile.  A block takes its tile index from the ticket when it starts, so
+// tiles start in index order and a tile only waits for tiles that started
+// before it: every wait ends.  The ticket's high half is the launch's epoch,
+// the tag of its status words; the block that draws count G-1 -- every
+// block of the launch has drawn by then -- re-arms the count and advances
+// the epoch.  One atomic per tile, nothing to clear between launches.
 #include "cls_scan.hpp"
 
 namespace spmd {
@@ -16,7 +17,7 @@ constexpr size_t SCAN_WS_HEADER = 256;
 template <int B, int I>
 __global__ __launch_bounds__(B) void scan_i32_kernel(const int32_t* __restrict__ x, int32_t* __restrict__ y,
                                                       uint32_t n, uint32_t* ws, uint32_t* err, bool vec) {
-    __shared__ ScanLds<B> L;
+    __shared__ ScanLds<B, I> L;
     __shared__ uint32_t s_tile, s_tag;
     uint64_t* ticket = reinterpret_cast<uint64_t*>(ws);
     uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + SCAN_WS_HEADER);
@@ -63,7 +64,8 @@ int launch_scan_i32(const LaunchCtx& c) {
     if (I > 32) return SPMD_ERR_INVALID_DIM;
     if (n == 0) return SPMD_OK;
     const bool vec = aligned(x, 16) && aligned(y, 16);
-    dim3 g(c.grid.x);
+    const uint32_t G = c.grid.x;
+    dim3 g(G);
     uint32_t* err = c.dev->err_word;
     switch (B) {
     case 64: launch_b<64>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;

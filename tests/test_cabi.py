@@ -57,7 +57,7 @@ def test_error_strings(spmd):
 
 
 def test_workspace_sizes(spmd):
-    assert spmd.workspace_size(spmd.REDUCE_I32, 4096, 256, 1 << 20) == 256 + 8 * 4096
+    assert spmd.workspace_size(spmd.REDUCE_I32, 4096, 256, 1 << 20) == 65 * 128 + 8 * 4096
     assert spmd.workspace_size(spmd.SCAN_I32, 8192, 512, 1 << 26) == 256 + 8 * 8192
     assert spmd.workspace_size(spmd.HIST256_U32, 10, 256, 100) == 0
     assert spmd.workspace_size(99, 1, 1, 1) == 0
@@ -138,7 +138,7 @@ def test_batch_workspace_and_validation(spmd):
                              (J, 30, 20, (256, 2, 2))])
     size = lib.spmd_batch_workspace_size(arr, sch, 4)
     # run area (cursors + reduce ticket/status + scan status) + baseline scratch + 4 descriptors + maps
-    assert size >= 256 + (256 + 8 * 4) + 8 * 20 + 4 * 64 and size % 256 == 0
+    assert size >= 256 + (65 * 128 + 8 * 4) + 8 * 20 + 4 * 64 and size % 256 == 0
     h = ctypes.c_void_p()
     # workspace checks come before any device work
     assert lib.spmd_batch_create(arr, sch, 4, None, size, 0, ctypes.byref(h)) == -8

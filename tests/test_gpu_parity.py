@@ -266,3 +266,20 @@ def test_gemm_workload_size(spmd, tile):
     c64 = oracle.gemm_f64_entries(A, B, ii, jj)
     d = np.abs(C[ii, jj].astype(np.float64) - c64)
     assert d.max() / np.abs(c64).max() <= 1e-5 * np.sqrt(n)
+
+
+def test_scan_forms_share_a_workspace(spmd):
+    """Small item counts run one workgroup per tile (ticket order), larger
+    ones the persistent cooperative form; both advance the same epoch, so
+    alternating them on one workspace must stay exact."""
+    n = 300_007
+    say("scan alternating forms", n)
+    x = synth.uniform_int32(17, n, -(2**31), 2**31 - 1)
+    want = oracle.scan_i32(x, 64, 4)
+    xt = dev(x)
+    grid_max = spmd.ops.scan_grid(n, 64, 1)
+    ws = spmd.ops.workspace(spmd.SCAN_I32, grid_max, 64, n)
+    for block, items in [(64, 1), (256, 8), (64, 2), (512, 16), (128, 4), (1024, 32), (64, 1)]:
+        y = spmd.ops.scan_i32(xt, block, items, ws=ws)
+        spmd.sync()
+        assert np.array_equal(host(y), want), (block, items)
