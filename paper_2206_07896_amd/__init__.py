@@ -168,3 +168,4 @@ def sync_timeout(stream=None, ms: int = 10000) -> None:
 
 from . import ops  # noqa: E402,F401  (tensor-level helpers)
 from . import batch  # noqa: E402,F401  (persistent block queue, device inputs)
+from . import learned  # noqa: E402,F401  (autotuner and learned cost model)

@@ -1,0 +1,96 @@
+"""Pins of the FP64 cost-model oracle: central finite differences of the
+loss, special cases with known gradients, and Adam's first step."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _data(n=37, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, mlp.DIN))
+    t = rng.standard_normal(n)
+    return X, t
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gradient_matches_central_differences(seed):
+    X, t = _data(seed=seed)
+    mu = X.mean(axis=0)
+    inv_sd = 1.0 / (X.std(axis=0) + 0.5)
+    p = mlp.init_params(seed)
+    p[mlp.NPARAM - 1] = 0.3
+    g = mlp.grad(p, X, t, mu, inv_sd)
+    rng = np.random.default_rng(seed + 10)
+    idx = rng.choice(mlp.NPARAM, 200, replace=False)
+    h = 1e-6
+    fd = np.empty(idx.size)
+    for k, i in enumerate(idx):
+        e = np.zeros(mlp.NPARAM)
+        e[i] = h
+        fd[k] = (mlp.loss(p + e, X, t, mu, inv_sd) - mlp.loss(p - e, X, t, mu, inv_sd)) / (2 * h)
+    # kinks of relu are measure-zero for random data; compare normwise
+    assert np.linalg.norm(fd - g[idx]) <= 1e-6 * np.linalg.norm(g[idx])
+
+
+def test_zero_weights_output_is_bias_and_only_b3_learns():
+    X, t = _data()
+    p = np.zeros(mlp.NPARAM)
+    p[-1] = 1.25
+    y, _ = mlp.forward(p, X)
+    assert np.all(y == 1.25)
+    g = mlp.grad(p, X, t)
+    # every hidden unit is dead (z = 0, relu' = 0): only b3 has a gradient
+    assert np.all(g[:-1] == 0.0)
+    assert g[-1] == pytest.approx(2.0 * np.mean(1.25 - t), rel=1e-14)
+
+
+def test_dead_first_layer_unit_has_zero_gradient():
+    X, t = _data()
+    d = mlp.unpack(mlp.init_params(3))
+    d["b1"][5] = -1e6  # unit 5 of layer 1 is never active
+    g = mlp.unpack(mlp.grad(mlp.pack(d), X, t))
+    assert np.all(g["W1"][:, 5] == 0.0) and g["b1"][5] == 0.0
+    assert np.all(g["W2"][5, :] == 0.0)
+
+
+def test_linear_regime_matches_least_squares_gradient():
+    # with every unit active and W2 = I, the model is affine in xn: y = xn A + c
+    X, t = _data(n=50, seed=4)
+    d = mlp.unpack(np.zeros(mlp.NPARAM))
+    rng = np.random.default_rng(5)
+    d["W1"] = rng.standard_normal((mlp.DIN, mlp.H)) * 0.01
+    d["b1"][:] = 100.0
+    d["W2"] = np.eye(mlp.H)
+    d["w3"] = rng.standard_normal(mlp.H)
+    p = mlp.pack(d)
+    y, _ = mlp.forward(p, X)
+    A = d["W1"] @ d["w3"]
+    c = d["b1"] @ d["w3"]
+    assert np.allclose(y, X @ A + c, rtol=1e-12, atol=1e-9)
+    # d loss / d b3 = mean(2 (y - t))
+    assert mlp.grad(p, X, t)[-1] == pytest.approx(np.mean(2 * (y - t)), rel=1e-12)
+
+
+def test_adam_first_step_is_lr_times_sign():
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    p1, m1, v1 = mlp.adam_step(p, g, m, v, 1, 0.01, eps=0.0)
+    # bias-corrected first moments equal g and |g|: the step is lr * sign(g)
+    assert np.allclose(p1, p - 0.01 * np.sign(g), rtol=0, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+
+
+def test_training_reduces_loss():
+    X, _ = _data(n=256, seed=7)
+    t = np.sin(X[:, 0]) + 0.5 * X[:, 1] ** 2
+    p = mlp.init_params(1)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    l0 = mlp.loss(p, X, t)
+    for s in range(1, 301):
+        p, m, v = mlp.adam_step(p, mlp.grad(p, X, t), m, v, s, 3e-3)
+    assert mlp.loss(p, X, t) < 0.2 * l0
