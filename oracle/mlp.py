@@ -91,3 +91,26 @@ def init_params(seed: int, scale1: float = None, scale2: float = None) -> np.nda
         "b3": np.zeros(1),
     }
     return pack(d)
+
+
+def ensemble_choose(params_list, feats, cands, valid, mu=None, inv_sd=None):
+    """Schedule choice of an ensemble: for each launch (row of feats) every
+    valid candidate (row of cands) is scored by the mean prediction of the
+    models; the chosen index minimises it (the lowest index among equal
+    means).  Returns (index, mean there, population standard deviation of
+    the models' predictions there); index -1 when no candidate is valid."""
+    feats = np.asarray(feats, dtype=np.float64)
+    cands = np.asarray(cands, dtype=np.float64)
+    m, c = feats.shape[0], cands.shape[0]
+    best = np.full(m, -1, dtype=np.int64)
+    mean_at = np.full(m, np.inf)
+    sd_at = np.zeros(m)
+    for i in range(m):
+        X = np.concatenate([np.repeat(feats[i:i + 1], c, axis=0), cands], axis=1)
+        preds = np.stack([forward(p, X, mu, inv_sd)[0] for p in params_list])
+        mean = preds.mean(axis=0)
+        sd = preds.std(axis=0)
+        for j in range(c):
+            if valid[i][j] and (best[i] < 0 or mean[j] < mean_at[i]):
+                best[i], mean_at[i], sd_at[i] = j, mean[j], sd[j]
+    return best, mean_at, sd_at

@@ -186,15 +186,23 @@ __global__ __launch_bounds__(SPMD_MLP_MAX_CANDS) void mlp_choose_kernel(
             for (int q = 0; q < SPMD_MLP_NFEAT; ++q) xrow[q] = feats[(uint64_t)li * SPMD_MLP_NFEAT + q];
 #pragma unroll
             for (int q = 0; q < SPMD_MLP_NSCHED; ++q) xrow[SPMD_MLP_NFEAT + q] = cands[j * SPMD_MLP_NSCHED + q];
-            float s1 = 0.0f, s2 = 0.0f;
-            for (uint32_t mk = 0; mk < k_models; ++mk) {
-                const float pr = row_forward<false>(P + mk * NP, nm, xrow, 0, 0, nullptr, nullptr);
-                s1 += pr;
-                s2 += pr * pr;
+            // two passes (mean, then squared deviations): the spread of
+            // nearly equal predictions keeps its precision
+            float pr[SPMD_MLP_MAX_MODELS];
+            float s1 = 0.0f;
+#pragma unroll
+            for (uint32_t mk = 0; mk < SPMD_MLP_MAX_MODELS; ++mk) {
+                pr[mk] = mk < k_models ? row_forward<false>(P + mk * NP, nm, xrow, 0, 0, nullptr, nullptr) : 0.0f;
+                s1 += pr[mk];
             }
             mean = s1 / (float)k_models;
-            const float var = s2 / (float)k_models - mean * mean;
-            sd = var > 0.0f ? sqrtf(var) : 0.0f;
+            float s2 = 0.0f;
+#pragma unroll
+            for (uint32_t mk = 0; mk < SPMD_MLP_MAX_MODELS; ++mk) {
+                const float d = pr[mk] - mean;
+                s2 += mk < k_models ? d * d : 0.0f;
+            }
+            sd = sqrtf(s2 / (float)k_models);
         }
         red_v[j] = mean;
         red_i[j] = ok ? j : 0xFFFFFFFFu;
@@ -275,6 +283,11 @@ int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, c
     if (m && (!feats || !valid || !best || !best_pred || !best_sd)) return SPMD_ERR_ARGS;
     if (!m) return SPMD_OK;
     const size_t shm = (size_t)k_models * NP * sizeof(float);
+    if (shm > 65536) {  // up to 4 models: 81 KB of the 160 KB LDS, opted in explicitly
+        hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&mlp_choose_kernel),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (ea != hipSuccess) return hip_fail(ea);
+    }
     const uint32_t grid = m < 1024 ? m : 1024;
     hipLaunchKernelGGL(mlp_choose_kernel, dim3(grid), dim3(SPMD_MLP_MAX_CANDS), shm, static_cast<hipStream_t>(stream),
                        params, k_models, norm, feats, m, cands, c, valid, best, best_pred, best_sd);

@@ -94,3 +94,40 @@ def test_training_reduces_loss():
     for s in range(1, 301):
         p, m, v = mlp.adam_step(p, mlp.grad(p, X, t), m, v, s, 3e-3)
     assert mlp.loss(p, X, t) < 0.2 * l0
+
+
+def test_ensemble_choose_special_cases():
+    rng = np.random.default_rng(11)
+    feats = rng.standard_normal((5, 9))
+    cands = rng.standard_normal((7, 3))
+    valid = np.ones((5, 7), bool)
+    valid[1, :3] = False
+    valid[2, :] = False
+    # constant models: every candidate ties, the first valid index wins
+    const = np.zeros(mlp.NPARAM)
+    const[-1] = 2.0
+    best, mean, sd = mlp.ensemble_choose([const, const], feats, cands, valid)
+    assert list(best) == [0, 3, -1, 0, 0]
+    assert mean[0] == 2.0 and sd[0] == 0.0
+    # one model: the choice is the argmin of its own predictions over the valid set
+    p = mlp.init_params(4)
+    best, mean, sd = mlp.ensemble_choose([p], feats, cands, valid)
+    for i in (0, 1, 3, 4):
+        y, _ = mlp.forward(p, np.concatenate([np.repeat(feats[i:i + 1], 7, 0), cands], 1))
+        y = np.where(valid[i], y, np.inf)
+        assert best[i] == int(np.argmin(y)) and mean[i] == y[best[i]] and sd[i] == 0.0
+
+
+def test_ensemble_choose_mean_and_sd_of_two_models():
+    # two models that differ only in b3 by +-d: mean is the shared part, sd = d
+    rng = np.random.default_rng(12)
+    feats = rng.standard_normal((3, 9))
+    cands = rng.standard_normal((4, 3))
+    p = mlp.init_params(5)
+    a, b = p.copy(), p.copy()
+    a[-1] += 0.75
+    b[-1] -= 0.75
+    best, mean, sd = mlp.ensemble_choose([a, b], feats, cands, np.ones((3, 4), bool))
+    best1, mean1, _ = mlp.ensemble_choose([p], feats, cands, np.ones((3, 4), bool))
+    assert list(best) == list(best1)
+    assert np.allclose(mean, mean1, rtol=0, atol=1e-12) and np.allclose(sd, 0.75, rtol=0, atol=1e-12)
