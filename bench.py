@@ -1,7 +1,7 @@
 """Benchmark of the SPMD kernel-grid executor on one MI355X.
 
 One step = one pass of the warp-primitive workload through the C ABI:
-  * SCAN_I32 over 2^26 int32 uniform in [0, 100], blockDim 512 (16 items
+  * SCAN_I32 over 2^26 int32 uniform in [0, 100], blockDim 512 (32 items
     per thread, single pass with decoupled look-back), then
   * HIST256_U32 over 2^27 uint32 keys drawn Zipf(1.1) over 256 bins with
     per-block LDS sub-histograms.
@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-launch queue")
     ap.add_argument("--mixed-count", type=int, default=10000)
+    ap.add_argument("--learned-eval", type=int, default=0, metavar="HELDOUT",
+                    help="also tune, train and score the cost model on this many held-out launches "
+                         "(500 training launches; minutes of GPU time)")
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     args = ap.parse_args()
@@ -215,6 +218,12 @@ def main():
     if not args.no_mixed:
         mixed = mixed_queue(spmd, args.mixed_count)
 
+    learned_eval = None
+    if args.learned_eval:
+        from paper_2206_07896_amd import learned as L
+
+        learned_eval, _ = L.evaluate(train_count=500, heldout_count=args.learned_eval, log=log)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(xs_h, ks_h, step_bytes)
@@ -244,6 +253,8 @@ def main():
         "kernels": kernels,
         "mixed_queue": mixed,
     }
+    if learned_eval is not None:
+        out["learned_schedule_eval"] = learned_eval
     print(json.dumps(out), flush=True)
 
 
@@ -320,21 +331,27 @@ def extra_workloads(spmd, synth):
 def mixed_queue(spmd, count, reps=10):
     """Mixed launches: `count` instances (class uniform over reduce, scan,
     hist, jacobi; n = round(2^U), U ~ U[10, 22]; blockDim uniform over
-    64..512) run as one persistent-queue batch replayed from a hipGraph,
-    against one launch per instance from a host loop.  Same schedule for
-    both (the instance's blockDim, 4 items per thread, average
-    coarse-grained fetching); outputs must agree bit for bit."""
+    64..512), each written as a CUDA launch with its blockDim and 4 items
+    per thread.  Compared on the same inputs:
+      * one launch per instance from a host loop (hardware block dispatch),
+        the baseline;
+      * the persistent queue replayed from a hipGraph with the same
+        schedule and the paper's average coarse-grained fetching;
+      * the persistent queue replayed from a hipGraph with the schedule the
+        shipped cost model picks (when the package holds one).
+    Outputs must agree bit for bit."""
     import torch
 
+    from paper_2206_07896_amd import learned as L
     from paper_2206_07896_amd import workload as W
 
     log(f"mixed queue: {count} instances")
     specs = W.mixed_specs(count)
     data = W.MixedData(specs)
-    sched = W.as_launched_schedules(specs)
-    b = spmd.batch.Batch(data.items(), sched)
+    heur = W.as_launched_schedules(specs)
+    b = spmd.batch.Batch(data.items(), heur)
     st = b.stats()
-    data.outputs.fill_(-1)  # same padding bytes between instances in both runs
+    data.outputs.fill_(-1)  # same padding bytes between instances in every run
     b.graph_launch()
     spmd.sync()
     ref = data.outputs.clone()
@@ -342,32 +359,51 @@ def mixed_queue(spmd, count, reps=10):
     b.launch_each()
     spmd.sync()
     same = bool(torch.equal(ref, data.outputs))
-    del ref
     t_graph = measure(b.graph_launch, reps, warmup=2)
-    t_eager = measure(b.launch, reps, warmup=1)
     t_each = measure(b.launch_each, max(3, reps // 2), warmup=1)
     spmd.sync()
+    b.close()
     gbytes = data.total_bytes / 1e9
     res = {
         "instances": count,
         "logical_blocks": st["blocks"],
-        "chunks": st["chunks"],
-        "kernel_launches_persistent": st["persistent_launches"],
         "kernel_launches_one_by_one": st["each_launches"],
-        "outputs_identical": same,
-        "ms_persistent_graph": round(t_graph, 3),
-        "ms_persistent_eager": round(t_eager, 3),
         "ms_one_by_one": round(t_each, 3),
-        "launches_per_s_persistent_graph": round(count / (t_graph * 1e-3), 1),
         "launches_per_s_one_by_one": round(count / (t_each * 1e-3), 1),
-        "speedup_vs_one_by_one": round(t_each / t_graph, 3),
-        "GB/s_persistent_graph": round(gbytes / (t_graph * 1e-3), 1),
-        "frac_hbm_persistent_graph": round(gbytes / (t_graph * 1e-3) / HBM_PEAK_GBS, 4),
-        "schedule": "blockDim as launched, 4 items/thread, average coarse-grained fetching ceil(blocks/pool)",
+        "heuristic": {"schedule": "blockDim as launched, 4 items/thread, average coarse-grained fetching "
+                                  "ceil(blocks/pool)",
+                      "chunks": st["chunks"], "kernel_launches": st["persistent_launches"],
+                      "ms_graph": round(t_graph, 3),
+                      "launches_per_s": round(count / (t_graph * 1e-3), 1),
+                      "speedup_vs_one_by_one": round(t_each / t_graph, 3),
+                      "GB/s": round(gbytes / (t_graph * 1e-3), 1)},
     }
-    log(f"mixed: graph {t_graph:.2f} ms, eager {t_eager:.2f} ms, one-by-one {t_each:.2f} ms, same={same}")
-    b.close()
-    del data
+    log(f"mixed: one-by-one {t_each:.2f} ms, heuristic graph {t_graph:.2f} ms")
+    model = L.load_default()
+    if model is not None:
+        choice, _, sd = model.choose(specs)
+        sched = [L.CANDIDATES[j] for j in choice]
+        bl = spmd.batch.Batch(data.items(), sched)
+        stl = bl.stats()
+        data.outputs.fill_(-1)
+        bl.graph_launch()
+        spmd.sync()
+        same = same and bool(torch.equal(ref, data.outputs))
+        t_l = measure(bl.graph_launch, reps, warmup=2)
+        spmd.sync()
+        bl.close()
+        res["learned"] = {"schedule": "cost model (ensemble argmin of predicted time), no fallback",
+                          "chunks": stl["chunks"], "kernel_launches": stl["persistent_launches"],
+                          "ms_graph": round(t_l, 3),
+                          "launches_per_s": round(count / (t_l * 1e-3), 1),
+                          "speedup_vs_one_by_one": round(t_each / t_l, 3),
+                          "speedup_vs_heuristic": round(t_graph / t_l, 3),
+                          "GB/s": round(gbytes / (t_l * 1e-3), 1),
+                          "frac_hbm": round(gbytes / (t_l * 1e-3) / HBM_PEAK_GBS, 4),
+                          "low_confidence_launches": int((sd > model.tau).sum())}
+        log(f"mixed: learned graph {t_l:.2f} ms")
+    res["outputs_identical"] = same
+    del ref, data
     torch.cuda.empty_cache()
     return res
 

@@ -103,6 +103,84 @@ int spmd_batch_destroy(spmd_batch* b);
  * ceil(blocks / pool) blocks per fetch (Section IV-A). */
 int spmd_batch_pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, uint32_t* pool);
 
+
+/* ---- CUDA-style launch descriptors (the batch form of spmd_launch) ---- */
+
+/* One launch as spmd_launch would take it: kernel id, grid, block, dynamic
+ * shared memory bytes and the packed argument pointers (read during the
+ * call only).  Batchable classes and their arguments:
+ *   SPMD_REDUCE_I32   x, partials, out, n, workspace   (only `out` is written:
+ *                     the batch keeps block partials in its own scratch)
+ *   SPMD_SCAN_I32     x, y, n, workspace               (workspace unused)
+ *   SPMD_HIST256_U32  keys, hist, n
+ *   SPMD_JACOBI5_F32  u, u_next, nx, ny
+ * The blockDim (product of `block`) is kept as the instance's launched
+ * block size; the grid fixes the elements per thread of the as-launched
+ * schedule. */
+typedef struct {
+    int kernel_id;
+    spmd_dim3 grid, block;
+    uint32_t dyn_shmem;
+    void** args;
+} spmd_launch_desc;
+
+enum {
+    /* blockDim as launched (rounded down to 64..512, a power of two),
+     * elements per thread from grid x block, and the paper's average
+     * coarse-grained fetching, ceil(blocks / pool) per fetch (Section IV-A) */
+    SPMD_SCHED_AS_LAUNCHED = 0,
+    /* the schedule of least predicted time under the loaded cost model
+     * (spmd_model_load); launches whose ensemble spread exceeds the model's
+     * threshold are tuned exhaustively instead (spmd_tune_time over every
+     * candidate), and that choice is cached by (class, sizes, blockDim) */
+    SPMD_SCHED_LEARNED = 1
+};
+
+/* Workspace bytes that spmd_launch_batch needs for these launches under
+ * any schedule (0 if a launch is invalid for batching). */
+size_t spmd_launch_batch_workspace_size(const spmd_launch_desc* descs, int n);
+
+/* Run n independent launches as one batch on `stream` (persistent workers
+ * draining the block queue).  Waits for earlier work on `stream` before
+ * reusing `workspace` (device memory, 256-byte aligned, caller-owned, alive
+ * until the batch completes), chooses the schedules, uploads the plan and
+ * enqueues it; returns without waiting for the batch.  Results are those
+ * of spmd_launch on each descriptor alone (REDUCE: `out` only).
+ * SPMD_ERR_ARGS for SPMD_SCHED_LEARNED without a loaded model. */
+int spmd_launch_batch(const spmd_launch_desc* descs, int n, int schedule_mode, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* How the last spmd_launch_batch call on this thread chose its schedules. */
+typedef struct {
+    uint32_t launches;
+    uint32_t by_model;       /* chosen by the cost model                     */
+    uint32_t tuned;          /* model not confident: tuned exhaustively now  */
+    uint32_t cached;         /* model not confident: earlier tuning reused   */
+} spmd_batch_report;
+int spmd_launch_batch_report(spmd_batch_report* out);
+
+/* Load the cost model used by SPMD_SCHED_LEARNED on the current device:
+ * k_models parameter vectors of SPMD_MLP_NPARAM floats and the input
+ * normalisation (mu[12] then inv_sd[12]), host pointers copied by the
+ * call; sd_threshold is the ensemble spread above which the exhaustive
+ * fallback runs (INFINITY: never; a negative value: always).  Replaces an
+ * earlier model and clears the tuned-schedule cache; k_models == 0 unloads
+ * the model (params and norm may then be NULL).  The device copies are the
+ * library's own until the next load or unload. */
+int spmd_model_load(const float* params, uint32_t k_models, const float* norm, float sd_threshold);
+
+/* The candidate schedules the tuner and the cost model range over, in
+ * their fixed order (block 64..512, then items 1..16, then bpf 1..32);
+ * writes up to `cap` of them and returns how many there are. */
+uint32_t spmd_sched_candidates(spmd_schedule* out, uint32_t cap);
+
+/* The 9 launch features of an instance as the cost model sees them: class
+ * one-hot (REDUCE, SCAN, HIST, JACOBI), log2 of its elements (JACOBI:
+ * nx * ny), log2 of its blockDim, log2 of the shared-memory bytes and the
+ * barriers per block and warp-level operations per warp of the class's
+ * block program at that blockDim. */
+int spmd_sched_features(const spmd_batch_item* item, float* out9);
+
 #ifdef __cplusplus
 }
 #endif

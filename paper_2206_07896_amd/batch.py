@@ -164,3 +164,107 @@ def synth_zipf_u32(out: torch.Tensor, seed: int, cdf: torch.Tensor, start: int =
     _check(_lib.spmd_synth_zipf_u32(out.data_ptr(), out.numel(), seed, start, cdf.data_ptr(), cdf.numel(),
                                     _stream_handle(stream)), "spmd_synth_zipf_u32")
     return out
+
+
+# ---- CUDA-style launch descriptors run as one batch (spmd_launch_batch) ----
+
+SCHED_AS_LAUNCHED = 0
+SCHED_LEARNED = 1
+
+
+class LaunchDesc(ctypes.Structure):
+    _fields_ = [("kernel_id", ctypes.c_int32), ("grid", _U32 * 3), ("block", _U32 * 3), ("dyn_shmem", _U32),
+                ("args", ctypes.POINTER(_P))]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("launches", _U32), ("by_model", _U32), ("tuned", _U32), ("cached", _U32)]
+
+
+_lib.spmd_launch_batch_workspace_size.argtypes = [ctypes.POINTER(LaunchDesc), ctypes.c_int]
+_lib.spmd_launch_batch_workspace_size.restype = ctypes.c_size_t
+_lib.spmd_launch_batch.argtypes = [ctypes.POINTER(LaunchDesc), ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P]
+_lib.spmd_launch_batch.restype = ctypes.c_int
+_lib.spmd_launch_batch_report.argtypes = [ctypes.POINTER(BatchReport)]
+_lib.spmd_launch_batch_report.restype = ctypes.c_int
+_lib.spmd_model_load.argtypes = [_P, _U32, _P, ctypes.c_float]
+_lib.spmd_model_load.restype = ctypes.c_int
+_lib.spmd_sched_candidates.argtypes = [ctypes.POINTER(Schedule), _U32]
+_lib.spmd_sched_candidates.restype = _U32
+_lib.spmd_sched_features.argtypes = [ctypes.POINTER(BatchItem), ctypes.POINTER(ctypes.c_float)]
+_lib.spmd_sched_features.restype = ctypes.c_int
+
+
+def _dims(d):
+    d = tuple(d) if isinstance(d, (tuple, list)) else (d,)
+    d = d + (1,) * (3 - len(d))
+    return (_U32 * 3)(*map(int, d))
+
+
+class _Descs:
+    """Marshalled launch descriptors (kernel_id, grid, block, dyn_shmem,
+    args); keeps the packed argument objects alive."""
+
+    def __init__(self, launches):
+        from . import pack_args
+
+        self.n = len(launches)
+        self.arr = (LaunchDesc * self.n)()
+        self._keep = []
+        for i, (kid, grid, block, shmem, args) in enumerate(launches):
+            packed, keep = pack_args(kid, args)
+            self._keep.append((packed, keep))
+            self.arr[i] = LaunchDesc(int(kid), _dims(grid), _dims(block), int(shmem),
+                                     ctypes.cast(packed, ctypes.POINTER(_P)))
+
+
+def launch_batch_workspace_size(launches) -> int:
+    d = _Descs(launches)
+    return int(_lib.spmd_launch_batch_workspace_size(d.arr, d.n))
+
+
+def launch_batch(launches, mode: int = SCHED_AS_LAUNCHED, workspace=None, stream=None):
+    """Run launches [(kernel_id, grid, block, dyn_shmem, args), ...] as one
+    batch; returns the workspace tensor (keep it alive until the batch is
+    synchronised)."""
+    d = _Descs(launches)
+    size = int(_lib.spmd_launch_batch_workspace_size(d.arr, d.n))
+    if size == 0:
+        raise SpmdError(-2, "spmd_launch_batch_workspace_size (a launch cannot be batched)")
+    if workspace is None or workspace.numel() < size + 256:
+        workspace = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
+    off = (-workspace.data_ptr()) % 256
+    _check(_lib.spmd_launch_batch(d.arr, d.n, int(mode), workspace.data_ptr() + off, workspace.numel() - off,
+                                  _stream_handle(stream)), "spmd_launch_batch")
+    return workspace
+
+
+def launch_batch_report() -> dict:
+    r = BatchReport()
+    _check(_lib.spmd_launch_batch_report(ctypes.byref(r)), "spmd_launch_batch_report")
+    return {"launches": r.launches, "by_model": r.by_model, "tuned": r.tuned, "cached": r.cached}
+
+
+def model_load(params, norm, sd_threshold: float = float("inf")) -> None:
+    """Load a cost model (host arrays: [k, NPARAM] parameters, 24 norm
+    values) for SCHED_LEARNED on the current device."""
+    import numpy as np
+
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    k = p.shape[0] if p.ndim == 2 else 1
+    nm = np.ascontiguousarray(norm, dtype=np.float32)
+    _check(_lib.spmd_model_load(p.ctypes.data, k, nm.ctypes.data, float(sd_threshold)), "spmd_model_load")
+
+
+def sched_candidates():
+    n = int(_lib.spmd_sched_candidates(None, 0))
+    arr = (Schedule * n)()
+    _lib.spmd_sched_candidates(arr, n)
+    return [(s.block, s.items, s.bpf) for s in arr]
+
+
+def sched_features(kernel_id: int, n: int, ny: int, block_dim: int):
+    it = BatchItem(int(kernel_id), int(n), int(ny), int(block_dim), None, None)
+    out = (ctypes.c_float * 9)()
+    _check(_lib.spmd_sched_features(ctypes.byref(it), out), "spmd_sched_features")
+    return list(out)

@@ -87,9 +87,9 @@ struct BatchLdsOf<SPMD_JACOBI5_F32, B> {
     };
 };
 
-template <int CLS, int B>
+template <int CLS, int B, typename Hook = NoHook>
 __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b, BatchLdsOf<CLS, B>& L,
-                                                  uint32_t* err) {
+                                                  uint32_t* err, Hook hook = Hook()) {
     const uint32_t t = threadIdx.x;
     if constexpr (CLS == SPMD_REDUCE_I32) {
         uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
@@ -102,11 +102,11 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
         uint64_t* st = reinterpret_cast<uint64_t*>(d.ws);
         const bool v = d.vec != 0u;
         switch (d.items) {
-        case 1: scan_tile<B, 1>(x, y, d.n, b, st, 0u, err, v, L.s1); break;
-        case 2: scan_tile<B, 2>(x, y, d.n, b, st, 0u, err, v, L.s2); break;
-        case 4: scan_tile<B, 4>(x, y, d.n, b, st, 0u, err, v, L.s4); break;
-        case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s8); break;
-        default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s16); break;
+        case 1: scan_tile<B, 1>(x, y, d.n, b, st, 0u, err, v, L.s1, hook); break;
+        case 2: scan_tile<B, 2>(x, y, d.n, b, st, 0u, err, v, L.s2, hook); break;
+        case 4: scan_tile<B, 4>(x, y, d.n, b, st, 0u, err, v, L.s4, hook); break;
+        case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s8, hook); break;
+        default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s16, hook); break;
         }
     } else if constexpr (CLS == SPMD_HIST256_U32) {
         const uint64_t lo = (uint64_t)b * d.aux;
@@ -127,6 +127,37 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
     }
 }
 
+// REDUCE and HIST: the logical blocks of one fetch cover one contiguous
+// element range, so they share one block body -- one LDS sub-histogram
+// flushed once, one partial published once -- instead of paying the flush
+// or the completion ticket per block.  Integer sums and counts do not
+// depend on how the range is cut, so the result is the same.
+template <int CLS, int B>
+__device__ __forceinline__ void run_fused_chunk(const BatchDesc& d, uint32_t q, uint32_t first, uint32_t last,
+                                                BatchLdsOf<CLS, B>& L, uint32_t* err) {
+    const uint64_t lo = (uint64_t)first * d.aux;
+    const uint64_t end = (uint64_t)last * d.aux;
+    const uint64_t hi = end < (uint64_t)d.n ? end : (uint64_t)d.n;
+    if constexpr (CLS == SPMD_REDUCE_I32) {
+        // chunk q of this instance is block q of a grid of ceil(nblocks / bpf)
+        // blocks whose segment is bpf * aux elements (the last one clamped)
+        const uint32_t nchunks = (d.nblocks + d.bpf - 1) / d.bpf;
+        const uint64_t seg64 = (uint64_t)d.aux * d.bpf;
+        const uint32_t seg = seg64 < (uint64_t)d.n ? (uint32_t)seg64 : (d.n ? d.n : 1u);
+        uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
+        uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + REDUCE_CTL_BYTES);
+        reduce_block<B>(reinterpret_cast<const int32_t*>(d.in), nullptr, reinterpret_cast<int32_t*>(d.out), d.n,
+                        seg, nchunks, q, ctl, status, 0u, err, d.vec != 0u, L.r);
+        (void)lo;
+        (void)hi;
+    } else {
+        hist_block<B, HIST_COPIES>(reinterpret_cast<const uint32_t*>(d.in), reinterpret_cast<uint32_t*>(d.out), lo,
+                                   hi, d.vec != 0u, L.h);
+        (void)q;
+        (void)err;
+    }
+}
+
 template <int CLS, int B>
 __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __restrict__ descs,
                                                               const uint32_t* __restrict__ chunk_inst,
@@ -140,18 +171,41 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
     uint32_t c = __builtin_amdgcn_readfirstlane(s_next);
     while (c < total_chunks) {
         __syncthreads();  // every thread has read s_next
+        // The next fetch is issued early so its round trip overlaps this
+        // chunk -- except for SCAN, where a reserved tile that has not
+        // started would hold up its successors' look-back while this worker
+        // is itself waiting in a look-back: SCAN fetches once its tile has
+        // published its inclusive prefix.
         uint32_t nxt = 0;
-        if (t == 0) nxt = atomic_add_dev(cursor, 1u);  // next fetch in flight during this chunk
+        bool fetched = false;
+        if (CLS != SPMD_SCAN_I32 && t == 0) {
+            nxt = atomic_add_dev(cursor, 1u);
+            fetched = true;
+        }
         const BatchDesc d = descs[chunk_inst[c]];
         const uint32_t first = (c - d.chunk0) * d.bpf;
         const uint32_t last = min(first + d.bpf, d.nblocks);
         if (t == 0 && (first >= last || d.cls != (uint32_t)CLS)) atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
         if (d.cls != (uint32_t)CLS) break;
-        for (uint32_t b = first; b < last; ++b) {
-            run_logical_block<CLS, B>(d, b, L, err);
-            __syncthreads();  // the next logical block reuses the LDS
+        if constexpr (CLS == SPMD_REDUCE_I32 || CLS == SPMD_HIST256_U32) {
+            run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
+            __syncthreads();
+        } else {
+            auto fetch_once = [&]() {
+                if (!fetched) {
+                    nxt = atomic_add_dev(cursor, 1u);
+                    fetched = true;
+                }
+            };
+            for (uint32_t b = first; b < last; ++b) {
+                run_logical_block<CLS, B>(d, b, L, err, fetch_once);
+                __syncthreads();  // the next logical block reuses the LDS
+            }
         }
-        if (t == 0) s_next = nxt;
+        if (t == 0) {
+            if (!fetched) nxt = atomic_add_dev(cursor, 1u);
+            s_next = nxt;
+        }
         __syncthreads();
         c = __builtin_amdgcn_readfirstlane(s_next);
     }
@@ -358,6 +412,7 @@ void launch_group(uint32_t block, dim3 gr, hipStream_t s, const BatchDesc* descs
 }
 
 int enqueue_run(spmd_batch* b, hipStream_t s) {
+    clear_stale_error();
     const uint64_t run_words = b->run_bytes / 16;
     const uint32_t zero_blocks = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, cdiv(run_words, 256)));
     hipLaunchKernelGGL(batch_prologue_kernel, dim3(b->nhist + zero_blocks), dim3(256), 0, s,

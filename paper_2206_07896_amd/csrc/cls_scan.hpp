@@ -110,12 +110,18 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
     return excl;
 }
 
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 // Scan tile `tile` of x into y.  The caller places a barrier before the LDS
-// area is reused.
-template <int B, int I>
+// area is reused.  Thread 0 calls `after_lookback` once the tile's
+// inclusive prefix is published, i.e. once no other tile can wait on this
+// one any more.
+template <int B, int I, typename Hook = NoHook>
 __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t* __restrict__ y, uint32_t n,
                                           uint32_t tile, uint64_t* status, uint32_t tag, uint32_t* err, bool vec,
-                                          ScanLds<B, I>& L) {
+                                          ScanLds<B, I>& L, Hook after_lookback = Hook()) {
     constexpr uint64_t T = (uint64_t)B * I;
     constexpr int NW = B / 32;
     constexpr int S = I / 4;  // 16-byte chunks per thread
@@ -166,7 +172,10 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
     }
     if (t < 64) {
         const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
-        if (t == 0) L.excl = excl;
+        if (t == 0) {
+            L.excl = excl;
+            after_lookback();
+        }
     }
     __syncthreads();
     const uint32_t pre = L.excl + wpre + (wincl - tot);

@@ -56,6 +56,12 @@ inline uint32_t segment_len(uint32_t n, uint32_t grid) {
 
 int hip_fail(hipError_t e);  // records the HIP error text, returns SPMD_ERR_HIP
 
+// The runtime keeps the error of the last failing call until it is read.
+// Entry points clear one that earlier, unrelated calls (another library's)
+// left behind before they launch, so the hipGetLastError after their
+// launches reports those launches only.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
 // State of the current device (created on first use with the device current).
 int runtime_dev(const DevInfo** out);
 

@@ -38,7 +38,14 @@ int launch_jacobi5_f32(const LaunchCtx& c) {
     if (C > 16) return SPMD_ERR_INVALID_DIM;
     dim3 g(c.grid.x, c.grid.y);
     const size_t d = c.dyn_shmem;
-    if (BX == 16 && BY == 16) launch_c<16, 16>(C, g, d, c.stream, u, v, nx, ny);
+    if (BX == 16 && BY == 16 && C <= 4) {
+        // Four consecutive logical blocks along x per workgroup (the
+        // coarse-grained fetch of Section IV-A, 4 blocks per fetch): their
+        // 64 x 16C region runs as 64 x 4 threads with 4C cells each, so
+        // every row of the LDS tile is one 256-byte segment instead of four
+        // 64-byte ones.  Each cell is computed exactly as in its own block.
+        launch_c<64, 4>(4 * C, dim3((c.grid.x + 3) / 4, c.grid.y), d, c.stream, u, v, nx, ny);
+    } else if (BX == 16 && BY == 16) launch_c<16, 16>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 64 && BY == 1) launch_c<64, 1>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 64 && BY == 2) launch_c<64, 2>(C, g, d, c.stream, u, v, nx, ny);
     else if (BX == 32 && BY == 8) launch_c<32, 8>(C, g, d, c.stream, u, v, nx, ny);

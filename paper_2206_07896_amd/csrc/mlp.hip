@@ -240,6 +240,7 @@ int spmd_mlp_forward(const float* params, const float* norm, const float* x, uin
                      float* h2t, void* stream) {
     if (!params || !norm || (n && (!x || !y)) || (!h1t) != (!h2t)) return SPMD_ERR_ARGS;
     if (!n) return SPMD_OK;
+    clear_stale_error();
     hipLaunchKernelGGL(mlp_forward_kernel, dim3((n + MLP_ROWS - 1) / MLP_ROWS), dim3(MLP_ROWS), 0,
                        static_cast<hipStream_t>(stream), params, norm, x, n, y, h1t, h2t);
     hipError_t e = hipGetLastError();
@@ -259,6 +260,7 @@ int spmd_mlp_backward(const float* params, const float* norm, const float* x, co
     const uint32_t nb = (n + MLP_ROWS - 1) / MLP_ROWS;
     hipStream_t s = static_cast<hipStream_t>(stream);
     float* part = static_cast<float*>(workspace);
+    clear_stale_error();
     hipLaunchKernelGGL(mlp_backward_kernel, dim3(nb), dim3(MLP_ROWS), 0, s, params, norm, x, t, n, y, h1t, h2t, part);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NP + 1 + 255) / 256), dim3(256), 0, s, part, nb, n, grad, loss);
     hipError_t e = hipGetLastError();
@@ -269,6 +271,7 @@ int spmd_mlp_adam(float* params, const float* grad, float* m, float* v, uint32_t
                   float beta2, float eps, void* stream) {
     if (!params || !grad || !m || !v || step == 0) return SPMD_ERR_ARGS;
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    clear_stale_error();
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
                        params, grad, m, v, lr, beta1, beta2, eps, c1, c2);
     hipError_t e = hipGetLastError();
@@ -289,6 +292,7 @@ int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, c
         if (ea != hipSuccess) return hip_fail(ea);
     }
     const uint32_t grid = m < 1024 ? m : 1024;
+    clear_stale_error();
     hipLaunchKernelGGL(mlp_choose_kernel, dim3(grid), dim3(SPMD_MLP_MAX_CANDS), shm, static_cast<hipStream_t>(stream),
                        params, k_models, norm, feats, m, cands, c, valid, best, best_pred, best_sd);
     hipError_t e = hipGetLastError();

@@ -120,6 +120,7 @@ int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem
     if (rc) return rc;
     if (dyn_shmem > di->max_shmem_per_block) return SPMD_ERR_SHMEM;
     LaunchCtx c{kernel_id, grid, block, dyn_shmem, args, static_cast<hipStream_t>(stream), di};
+    clear_stale_error();
     return ci->launch(c);
 }
 

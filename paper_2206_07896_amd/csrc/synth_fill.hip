@@ -47,6 +47,7 @@ static int fill(int kind, void* out, uint64_t count, uint64_t seed, uint64_t sta
     if (!out) return SPMD_ERR_ARGS;
     const uint64_t blocks = (count + 255) / 256;
     const uint32_t g = (uint32_t)(blocks < 16384 ? blocks : 16384);
+    clear_stale_error();
     hipLaunchKernelGGL(synth_fill_kernel, dim3(g), dim3(256), 0, static_cast<hipStream_t>(stream), kind, out, count,
                        sm_mix(seed), start, lo, span, cdf, k);
     hipError_t e = hipGetLastError();

@@ -27,6 +27,7 @@ from __future__ import annotations
 import ctypes
 import json
 import math
+import os
 
 import numpy as np
 import torch
@@ -36,10 +37,9 @@ from . import batch as B
 
 NFEAT, NSCHED, DIN, NPARAM = 9, 3, 12, 12 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 KIND_IDS = (REDUCE_I32, SCAN_I32, HIST256_U32, JACOBI5_F32)
-BLOCKS = (64, 128, 256, 512)
-ITEMS = (1, 2, 4, 8, 16)
-BPFS = (1, 2, 4, 8, 16, 32)
-CANDIDATES = [(b, it, f) for b in BLOCKS for it in ITEMS for f in BPFS]
+# the library's candidate table: block 64..512, items 1..16, bpf 1..32
+CANDIDATES = B.sched_candidates()
+BLOCKS = tuple(sorted({b for b, _, _ in CANDIDATES}))
 
 _P = ctypes.c_void_p
 _lib.spmd_mlp_forward.argtypes = [_P, _P, _P, ctypes.c_uint32, _P, _P, _P, _P]
@@ -71,18 +71,9 @@ def valid_candidates(kid: int) -> np.ndarray:
 
 
 def launch_features(spec) -> np.ndarray:
-    """The 9 launch features of a mixed-workload spec (see module doc)."""
-    kid, bd, n = spec["kid"], spec["block_dim"], max(1, spec["n"])
-    onehot = [1.0 if kid == k else 0.0 for k in KIND_IDS]
-    if kid == REDUCE_I32:
-        shm, bar, wops = 4 * bd, math.log2(bd) + 1, 0
-    elif kid == SCAN_I32:
-        shm, bar, wops = 4 * (bd // 32) + 4, 2, 10
-    elif kid == HIST256_U32:
-        shm, bar, wops = 1024, 2, 0
-    else:
-        shm, bar, wops = 4 * (bd // 64 + 2) * 66, 1, 0
-    return np.array(onehot + [math.log2(n), math.log2(bd), math.log2(shm), bar, wops], np.float32)
+    """The 9 launch features of a mixed-workload spec, as the library
+    computes them (spmd_sched_features)."""
+    return np.array(B.sched_features(spec["kid"], spec["nx"], spec["ny"], spec["block_dim"]), np.float32)
 
 
 def heuristic_schedule(spec, pools) -> tuple:
@@ -132,9 +123,10 @@ class Autotuner:
                "spmd_tune_time")
         return np.array(out[:], np.float64)
 
-    def sweep(self, specs, data, record=None):
+    def sweep(self, specs, data, progress=None):
         """Exhaustive timings: [len(specs), len(CANDIDATES)] ms, NaN where
-        a candidate is invalid for the class."""
+        a candidate is invalid for the class.  `progress` (a print-like
+        function) is called every 200 launches."""
         items = data.items()
         T = np.full((len(specs), len(CANDIDATES)), np.nan)
         f = open(self.db_path, "a") if self.db_path else None
@@ -145,10 +137,10 @@ class Autotuner:
             T[i, idx] = ms
             if f is not None:
                 f.write(json.dumps({"kid": s["kid"], "n": s["n"], "nx": s["nx"], "ny": s["ny"],
-                                    "block_dim": s["block_dim"], "ms": [float(v) for v in T[i]],
-                                    **(record or {})}) + "\n")
-            if record is not None and i % 200 == 0:
-                print(f"  tuned {i}/{len(specs)}", flush=True)
+                                    "block_dim": s["block_dim"],
+                                    "ms": [None if np.isnan(v) else float(v) for v in T[i]]}) + "\n")
+            if progress is not None and i % 200 == 0:
+                progress(f"  tuned {i}/{len(specs)}")
         if f is not None:
             f.close()
         return T
@@ -169,6 +161,7 @@ class CostModel:
         self.params = np.asarray(params, np.float32).reshape(-1, NPARAM)
         self.norm = np.asarray(norm, np.float32).reshape(2 * DIN)
         self.k = self.params.shape[0]
+        self.tau = float("inf")  # ensemble spread above which the exhaustive fallback runs
         self._dev = None
 
     def device_tensors(self):
@@ -178,12 +171,15 @@ class CostModel:
         return self._dev
 
     def to_json(self) -> str:
-        return json.dumps({"k": self.k, "norm": self.norm.tolist(), "params": self.params.tolist()})
+        return json.dumps({"k": self.k, "tau": self.tau, "norm": self.norm.tolist(),
+                           "params": self.params.tolist()})
 
     @staticmethod
     def from_json(text: str) -> "CostModel":
         d = json.loads(text)
-        return CostModel(np.array(d["params"], np.float32), np.array(d["norm"], np.float32))
+        m = CostModel(np.array(d["params"], np.float32), np.array(d["norm"], np.float32))
+        m.tau = float(d.get("tau", float("inf")))
+        return m
 
     def predict(self, X: np.ndarray, model: int = 0) -> np.ndarray:
         """Predicted log-microseconds of rows X[n x 12] under one model."""
@@ -252,7 +248,7 @@ def train(X: np.ndarray, t: np.ndarray, k_models: int = 3, steps: int = 3000, lr
     grad = torch.empty(NPARAM, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     s = _stream_handle(None)
-    out, losses = [], []
+    out, losses, first = [], [], []
     for k in range(k_models):
         p = torch.from_numpy(init_params(seed + 7919 * k)).cuda()
         m = torch.zeros(NPARAM, dtype=torch.float32, device="cuda")
@@ -265,11 +261,21 @@ def train(X: np.ndarray, t: np.ndarray, k_models: int = 3, steps: int = 3000, lr
                                           ws.data_ptr(), ws.numel(), s), "spmd_mlp_backward")
             _check(_lib.spmd_mlp_adam(p.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, 0.9, 0.999,
                                       1e-8, s), "spmd_mlp_adam")
+            if step == 1:
+                first.append(float(loss.item()))
             if log_every and step % log_every == 0:
                 print(f"  model {k} step {step} loss {float(loss.item()):.4f}", flush=True)
+        # the loss of the final parameters
+        _check(_lib.spmd_mlp_forward(p.data_ptr(), nm.data_ptr(), x.data_ptr(), n, y.data_ptr(), h1.data_ptr(),
+                                     h2.data_ptr(), s), "spmd_mlp_forward")
+        _check(_lib.spmd_mlp_backward(p.data_ptr(), nm.data_ptr(), x.data_ptr(), tt.data_ptr(), n, y.data_ptr(),
+                                      h1.data_ptr(), h2.data_ptr(), grad.data_ptr(), loss.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), s), "spmd_mlp_backward")
         losses.append(float(loss.item()))
         out.append(p.cpu().numpy())
-    return CostModel(np.stack(out), norm), losses
+    model = CostModel(np.stack(out), norm)
+    model.initial_losses = first
+    return model, losses
 
 
 def regret(T, choice):
@@ -277,3 +283,170 @@ def regret(T, choice):
     best = np.nanmin(T, axis=1)
     chosen = T[np.arange(T.shape[0]), choice]
     return (chosen - best) / best
+
+
+# ---------------------------------------------------------------------------
+# evaluation: exhaustive ground truth, training, held-out regret
+# ---------------------------------------------------------------------------
+
+def _median_graph_ms(batch, reps):
+    batch.graph_launch()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        batch.graph_launch()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-3, reps=2, fallback_quantile=0.9,
+             batch_reps=10, log=print, log2_hi=22.0):
+    """Exhaustively time `train_count` launches drawn like the mixed
+    workload (seed SEED_TRAIN) under every candidate schedule, train the
+    ensemble on the GPU, then choose schedules for `heldout_count` fresh
+    launches (seed SEED_HELDOUT) and score the choice against their own
+    exhaustive timings.  The fallback threshold is the `fallback_quantile`
+    of the ensemble spread over the training launches' choices; held-out
+    launches above it take the exhaustive choice."""
+    import time
+
+    import synth
+
+    from . import workload as W
+
+    pools = pools_for()
+    tuner = Autotuner(reps=reps)
+    t0 = time.perf_counter()
+    specs_tr = W.mixed_specs(train_count, seed=synth.SEED_TRAIN, log2_hi=log2_hi)
+    data_tr = W.MixedData(specs_tr)
+    log(f"c5: tuning {train_count} training launches x {len(CANDIDATES)} schedules")
+    T_tr = tuner.sweep(specs_tr, data_tr, progress=log)
+    del data_tr
+    t_tune_tr = time.perf_counter() - t0
+    X, t = training_rows(specs_tr, T_tr)
+    t1 = time.perf_counter()
+    model, losses = train(X, t, k_models=k_models, steps=steps, lr=lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"c5: trained {k_models} models on {X.shape[0]} rows in {t_train:.1f} s, final losses {losses}")
+    _, _, sd_tr = model.choose(specs_tr)
+    tau = float(np.quantile(sd_tr, fallback_quantile))
+
+    specs_ho = W.mixed_specs(heldout_count, seed=synth.SEED_HELDOUT, log2_hi=log2_hi)
+    data_ho = W.MixedData(specs_ho)
+    log(f"c5: tuning {heldout_count} held-out launches")
+    t2 = time.perf_counter()
+    T_ho = tuner.sweep(specs_ho, data_ho, progress=log)
+    t_tune_ho = time.perf_counter() - t2
+    items = data_ho.items()
+    heur = [heuristic_schedule(s, pools) for s in specs_ho]
+    t_heur = np.array([tuner.time(items[i], [heur[i]])[0] for i in range(heldout_count)])
+    t3 = time.perf_counter()
+    choice, pred, sd = model.choose(specs_ho)
+    torch.cuda.synchronize()
+    t_choose = time.perf_counter() - t3
+    exhaustive = np.nanargmin(T_ho, axis=1)
+    fb = sd > tau
+    choice_fb = np.where(fb, exhaustive, choice)
+    best = np.nanmin(T_ho, axis=1)
+    r_model = regret(T_ho, choice)
+    r_fb = regret(T_ho, choice_fb)
+    r_heur = (t_heur - best) / best
+    # log-time prediction error of the chosen schedules
+    chosen_t = T_ho[np.arange(heldout_count), choice]
+    pred_err = np.abs(pred - np.log(chosen_t * 1e3))
+
+    def batch_ms(scheds):
+        b = B.Batch(items, scheds)
+        try:
+            return _median_graph_ms(b, batch_reps)
+        finally:
+            b.close()
+
+    sched_learned = [CANDIDATES[j] for j in choice_fb]
+    sched_exh = [CANDIDATES[j] for j in exhaustive]
+    ms_learned = batch_ms(sched_learned)
+    ms_heur = batch_ms(heur)
+    ms_exh = batch_ms(sched_exh)
+    del data_ho
+    torch.cuda.empty_cache()
+    per_class = {}
+    for k in KIND_IDS:
+        sel = np.array([s["kid"] == k for s in specs_ho])
+        per_class[W.KIND_NAMES[k]] = {"launches": int(sel.sum()),
+                                      "regret_mean": round(float(r_model[sel].mean()), 4),
+                                      "regret_heuristic_mean": round(float(r_heur[sel].mean()), 4)}
+    res = {
+        "train_launches": train_count, "train_rows": int(X.shape[0]), "heldout_launches": heldout_count,
+        "candidates": len(CANDIDATES), "models": k_models, "adam_steps": steps,
+        "initial_train_mse": [round(v, 5) for v in model.initial_losses],
+        "final_train_mse": [round(v, 5) for v in losses],
+        "regret_mean": round(float(r_model.mean()), 4),
+        "regret_median": round(float(np.median(r_model)), 4),
+        "regret_mean_with_fallback": round(float(r_fb.mean()), 4),
+        "fallback_rate": round(float(fb.mean()), 4), "fallback_sd_threshold": round(tau, 4),
+        "regret_mean_heuristic": round(float(r_heur.mean()), 4),
+        "time_sum_ratio_heuristic_over_learned": round(float(t_heur.sum() / T_ho[np.arange(heldout_count), choice_fb].sum()), 3),
+        "abs_log_error_chosen_median": round(float(np.median(pred_err)), 4),
+        "per_class": per_class,
+        "batch_ms_learned": round(ms_learned, 3), "batch_ms_heuristic": round(ms_heur, 3),
+        "batch_ms_exhaustive": round(ms_exh, 3),
+        "launches_per_s_learned": round(heldout_count / (ms_learned * 1e-3), 1),
+        "launches_per_s_heuristic": round(heldout_count / (ms_heur * 1e-3), 1),
+        "launches_per_s_exhaustive": round(heldout_count / (ms_exh * 1e-3), 1),
+        "seconds": {"tune_train": round(t_tune_tr, 1), "train": round(t_train, 2),
+                    "tune_heldout": round(t_tune_ho, 1), "choose_2000": round(t_choose, 4)},
+        "heuristic": "instance blockDim, 4 items per thread, average coarse-grained fetching ceil(blocks/pool)",
+    }
+    log(f"c5: regret {res['regret_mean']:.3f} (with fallback {res['regret_mean_with_fallback']:.3f}, "
+        f"rate {res['fallback_rate']:.2f}), heuristic {res['regret_mean_heuristic']:.3f}; batch ms learned "
+        f"{ms_learned:.2f} heuristic {ms_heur:.2f} exhaustive {ms_exh:.2f}")
+    model.tau = tau
+    return res, model
+
+
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_model.json")
+
+
+def load_default():
+    """The cost model shipped with the package (trained on MI355X by
+    `python -m paper_2206_07896_amd.learned`), or None."""
+    if not os.path.exists(MODEL_PATH):
+        return None
+    with open(MODEL_PATH) as f:
+        return CostModel.from_json(f.read())
+
+
+def main(argv=None):
+    import argparse
+    import sys
+
+    ap = argparse.ArgumentParser(description="train and evaluate the schedule cost model on this GPU")
+    ap.add_argument("--train-count", type=int, default=500)
+    ap.add_argument("--heldout", type=int, default=2000)
+    ap.add_argument("--models", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--out", default=MODEL_PATH)
+    ap.add_argument("--report", default=None)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    res, model = evaluate(a.train_count, a.heldout, a.models, a.steps, log=log)
+    with open(a.out, "w") as f:
+        f.write(model.to_json())
+    text = json.dumps(res)
+    print(text, flush=True)
+    if a.report:
+        with open(a.report, "w") as f:
+            f.write(text + "\n")
+
+
+if __name__ == "__main__":
+    main()

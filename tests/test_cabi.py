@@ -6,6 +6,7 @@ import glob
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -152,3 +153,63 @@ def test_batch_workspace_and_validation(spmd):
     assert lib.spmd_batch_create(arr, sch, 0, 0x100000, 1 << 20, 0, ctypes.byref(h)) == -4
     assert lib.spmd_batch_launch(None, None) == -4
     assert lib.spmd_batch_destroy(None) == -4
+
+
+def test_schedule_candidates_table(spmd):
+    from paper_2206_07896_amd import batch as B
+
+    c = B.sched_candidates()
+    assert len(c) == 120 and len(set(c)) == 120
+    assert c[0] == (64, 1, 1) and c[-1] == (512, 16, 32)
+    assert sorted(c) == c  # block, then items, then bpf ascending
+    assert {b for b, _, _ in c} == {64, 128, 256, 512}
+    assert {i for _, i, _ in c} == {1, 2, 4, 8, 16}
+    assert {f for _, _, f in c} == {1, 2, 4, 8, 16, 32}
+
+
+def test_launch_features_closed_forms(spmd):
+    from paper_2206_07896_amd import batch as B
+
+    # REDUCE at blockDim 256: 1 KiB of shared memory, 8 tree levels + the load barrier
+    f = B.sched_features(spmd.REDUCE_I32, 1 << 20, 1, 256)
+    assert f == [1.0, 0.0, 0.0, 0.0, 20.0, 8.0, 10.0, 9.0, 0.0]
+    # SCAN at blockDim 512: 16 warp totals + the carry, two barriers, 2 x 5 shuffles
+    f = B.sched_features(spmd.SCAN_I32, 1 << 26, 1, 512)
+    assert f[:6] == [0.0, 1.0, 0.0, 0.0, 26.0, 9.0] and f[7:] == [2.0, 10.0]
+    assert abs(f[6] - np.log2(4 * 16 + 4)) < 1e-6
+    # JACOBI counts nx * ny elements
+    f = B.sched_features(spmd.JACOBI5_F32, 64, 32, 128)
+    assert f[3] == 1.0 and f[4] == 11.0 and f[5] == 7.0
+    # HIST, and n = 0 is treated as one element
+    f = B.sched_features(spmd.HIST256_U32, 0, 1, 64)
+    assert f[2] == 1.0 and f[4] == 0.0 and f[6] == 10.0
+
+
+def test_launch_batch_rejects_unbatchable_launches(spmd):
+    """Descriptor validation needs no device: the workspace query returns 0
+    for launches that cannot be batched."""
+    import ctypes as C
+
+    from paper_2206_07896_amd import batch as B
+
+    def desc(kid, grid, block, args):
+        arr = (C.c_void_p * len(args))(*args)
+        return B.LaunchDesc(kid, (C.c_uint32 * 3)(*grid), (C.c_uint32 * 3)(*block), 0,
+                            C.cast(arr, C.POINTER(C.c_void_p))), arr
+
+    n = C.c_uint32(1000)
+    p = C.c_void_p(0x1000)
+    ptrs = [C.cast(C.pointer(p), C.c_void_p).value] * 3 + [C.cast(C.pointer(n), C.c_void_p).value]
+    ok, keep = desc(spmd.HIST256_U32, (4, 1, 1), (256, 1, 1), ptrs[:2] + [ptrs[3]])
+    lib = spmd.lib()
+    one = (B.LaunchDesc * 1)(ok)
+    assert lib.spmd_launch_batch_workspace_size(one, 1) > 0
+    for kid, grid, block in ((spmd.GEMM_F32, (4, 1, 1), (256, 1, 1)),       # not a batchable class
+                             (spmd.HIST256_U32, (0, 1, 1), (256, 1, 1)),    # empty grid
+                             (spmd.HIST256_U32, (4, 1, 1), (2048, 1, 1))):  # block over 1024
+        bad, keep2 = desc(kid, grid, block, ptrs[:2] + [ptrs[3]])
+        assert lib.spmd_launch_batch_workspace_size((B.LaunchDesc * 1)(bad), 1) == 0
+    assert lib.spmd_launch_batch_workspace_size(one, 0) == 0
+    # learned mode without a model, bad mode, missing workspace: errors, no device work
+    assert lib.spmd_launch_batch(one, 1, 7, None, 0, None) == -4
+    assert lib.spmd_launch_batch(one, 1, 0, None, 0, None) == -8
