@@ -280,7 +280,32 @@ def extra_workloads(spmd, synth):
     ms = measure(lambda: spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr), 50)
     b = 4 * n + 4 * 4096 + 4
     res["reduce_i32 2^20 g4096 b256"] = {"us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1),
-                                        "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+                                        "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                        "timing": "events around each host launch"}
+    # the same launches replayed from a captured graph: device time without host launch cost
+    expect = int(synth.uniform_int32(synth.SEED_REDUCE, n, -1000, 1000).astype(np.int64).sum())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):
+            spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    per_graph = 20
+    with torch.cuda.graph(graph):
+        for _ in range(per_graph):
+            spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr)
+    for _ in range(3):  # every replay gives the eager result
+        o.fill_(0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(o.cpu()[0]) == expect
+    ms = measure(graph.replay, 20) / per_graph
+    res["reduce_i32 2^20 g4096 b256 (graph replay)"] = {
+        "us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1), "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+        "timing": f"one graph of {per_graph} launches, median replay / {per_graph}"}
+    del graph
     del x
     # the same class where HBM, not launch latency, decides: 2^28 (1 GiB) and 2^30 (4 GiB)
     for lg in (28, 30):

@@ -23,6 +23,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python paper_2206_07896_amd/build.py` "
         "(hipcc, gfx950); this package has no non-HIP implementation")
 
+# torch first: it ships its own HIP runtime under the same soname as the
+# system one the library links against, and the process shares whichever
+# is loaded first.  Loading torch's first keeps one runtime for both, so
+# device pointers and streams from torch are valid in the library.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 SPMD_OK = 0

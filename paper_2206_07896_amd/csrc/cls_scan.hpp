@@ -1,17 +1,27 @@
 // cls_scan.hpp -- tile body of the SCAN_I32 class (inclusive prefix sum
 // modulo 2^32).
 //
-// A tile is B threads x I consecutive items per thread:
-//   1. thread-serial inclusive scan of its I items (registers);
-//   2. 32-lane inclusive scan of the thread totals (warp32 DPP scan);
-//   3. the last lane of each warp writes the warp total to LDS; barrier;
-//      each thread adds the totals of the warps before its own;
-//   4. grid carry by decoupled look-back (Merrill and Garland, "Single-pass
+// A tile is B threads x I items: B*I consecutive elements.
+//   1. local scan.  A full, 16-byte aligned tile with I >= 4 is read in
+//      rows: wave w owns elements [w*64*I, (w+1)*64*I) of the tile and
+//      reads them as I/4 coalesced 1 KiB rows, lane l holding elements
+//      4l .. 4l+3 of each row.  Each row is scanned where it lies: the
+//      lane's four values, then the 32-lane inclusive scan of the lane
+//      totals on each half-wavefront (warp32 DPP scan), the two halves
+//      joined by lane 31's total, rows chained by their totals.  Any other
+//      tile gives each thread I consecutive items: thread-serial scan, then
+//      the 32-lane scan of the thread totals.
+//   2. the last lane of each wave (rows) or warp (items) writes its total
+//      to LDS; barrier; each thread adds the totals before its own;
+//   3. grid carry by decoupled look-back (Merrill and Garland, "Single-pass
 //      Parallel Prefix Scan with Decoupled Look-back", 2016): the tile
 //      publishes its aggregate, wave 0 reads the status words of up to 64
 //      predecessors at a time, sums aggregates back to the nearest inclusive
 //      prefix, and publishes its own inclusive prefix; barrier;
-//   5. every item gets carry + warp prefix + thread prefix.
+//   4. every item gets carry + its in-tile prefix and is stored (rows: as
+//      the same coalesced rows).
+// Values stay in registers from load to store, and LDS holds only the
+// per-wave totals, so residency is set by registers, not by a staging tile.
 // Tiles must start in index order (a ticket or an ordered queue hands the
 // indices out), so every predecessor a tile waits for has already started
 // and the waits end.  Each wait is still bounded: past the spin limit the
@@ -29,25 +39,9 @@ constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 22;
 
 template <int B, int I>
 struct ScanLds {
-    uint32_t warp[B / 32];
+    uint32_t warp[B / 32];  // warp totals (items path) or wave totals (rows path)
     uint32_t excl;
-    // Tile staging for I >= 4: the tile travels between HBM and registers
-    // through LDS so that global loads and stores are fully coalesced
-    // (lane-consecutive 16-byte chunks) while each thread still owns I
-    // consecutive items.
-    alignas(16) uint32_t tile[I >= 4 ? B * I : 4];
 };
-
-// LDS slot of 16-byte chunk c of a staged tile with S chunks per thread:
-// c ^ ((c / S) mod 8).  It permutes chunks within aligned groups of eight,
-// so that both the striped pass (lanes take consecutive chunks) and the
-// blocked pass (lane t takes chunks t*S .. t*S+S-1) touch eight distinct
-// slots per eight lanes: no LDS bank conflicts either way.
-template <int S>
-__device__ __forceinline__ uint32_t stage_slot(uint32_t c) {
-    if constexpr (S >= 2) return c ^ ((c / S) & 7u);
-    else return c;
-}
 
 // Exclusive carry of `tile`, computed by wave 0 (the 64 lanes call it).
 // Polling is the costly part on gfx950: every status read is a device-
@@ -123,39 +117,70 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
                                           uint32_t tile, uint64_t* status, uint32_t tag, uint32_t* err, bool vec,
                                           ScanLds<B, I>& L, Hook after_lookback = Hook()) {
     constexpr uint64_t T = (uint64_t)B * I;
-    constexpr int NW = B / 32;
-    constexpr int S = I / 4;  // 16-byte chunks per thread
     const uint32_t t = threadIdx.x;
     const uint64_t tbase = (uint64_t)tile * T;
-    const uint64_t base = tbase + (uint64_t)t * I;
-    // a full, aligned tile is staged through LDS; the rest is read directly
-    bool staged = false;
-    if constexpr (I >= 4) staged = vec && tbase + T <= (uint64_t)n;
-    uint32_t v[I];
     if constexpr (I >= 4) {
-        if (staged) {
-            const u32x4* xv = reinterpret_cast<const u32x4*>(x + tbase);
+        if (vec && tbase + T <= (uint64_t)n) {
+            constexpr int S = I / 4;  // rows per wave
+            constexpr int NWAVE = B / 64;
+            const uint32_t lane = lane64(), wave = t >> 6;
+            const uint64_t wbase = tbase + (uint64_t)wave * 64u * I;
+            const u32x4* xv = reinterpret_cast<const u32x4*>(x + wbase);
             u32x4 r[S];
 #pragma unroll
-            for (int q = 0; q < S; ++q) r[q] = __builtin_nontemporal_load(xv + q * B + t);
-            u32x4* st = reinterpret_cast<u32x4*>(L.tile);
+            for (int q = 0; q < S; ++q) r[q] = __builtin_nontemporal_load(xv + q * 64 + lane);
+            uint32_t carry = 0;  // wave-uniform: total of the rows before row q
 #pragma unroll
-            for (int q = 0; q < S; ++q) st[stage_slot<S>(q * B + t)] = r[q];
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const u32x4 a = st[stage_slot<S>(t * S + j)];
-                v[4 * j] = a.x;
-                v[4 * j + 1] = a.y;
-                v[4 * j + 2] = a.z;
-                v[4 * j + 3] = a.w;
+            for (int q = 0; q < S; ++q) {
+                r[q].y += r[q].x;
+                r[q].z += r[q].y;
+                r[q].w += r[q].z;
+                uint32_t incl = w32_inclusive_add(r[q].w);
+                incl += lane >= 32u ? (uint32_t)__builtin_amdgcn_readlane((int)incl, 31) : 0u;
+                const uint32_t before = incl - r[q].w + carry;
+                r[q].x += before;
+                r[q].y += before;
+                r[q].z += before;
+                r[q].w += before;
+                carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             }
+            if (lane == 0) L.warp[wave] = carry;
+            __syncthreads();
+            uint32_t wpre = 0, agg = 0;
+#pragma unroll
+            for (int w = 0; w < NWAVE; ++w) {
+                const uint32_t s = L.warp[w];
+                agg += s;
+                wpre += ((uint32_t)w < wave) ? s : 0u;
+            }
+            if (t < 64) {
+                const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
+                if (t == 0) {
+                    L.excl = excl;
+                    after_lookback();
+                }
+            }
+            __syncthreads();
+            const uint32_t pre = L.excl + wpre;
+            u32x4* yv = reinterpret_cast<u32x4*>(y + wbase);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                u32x4 a = r[q];
+                a.x += pre;
+                a.y += pre;
+                a.z += pre;
+                a.w += pre;
+                __builtin_nontemporal_store(a, yv + q * 64 + lane);
+            }
+            return;
         }
     }
-    if (!staged) {
+    // items path: partial or unaligned tiles, and I < 4
+    constexpr int NW = B / 32;
+    const uint64_t base = tbase + (uint64_t)t * I;
+    uint32_t v[I];
 #pragma unroll
-        for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
-    }
+    for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
 #pragma unroll
     for (int k = 1; k < I; ++k) v[k] += v[k - 1];
     const uint32_t tot = v[I - 1];
@@ -179,27 +204,6 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
     }
     __syncthreads();
     const uint32_t pre = L.excl + wpre + (wincl - tot);
-    if constexpr (I >= 4) {
-        if (staged) {
-            // each thread rewrites only the slots it read, then the tile
-            // leaves through LDS in lane-consecutive chunks
-            u32x4* st = reinterpret_cast<u32x4*>(L.tile);
-#pragma unroll
-            for (int j = 0; j < S; ++j) {
-                u32x4 a;
-                a.x = pre + v[4 * j];
-                a.y = pre + v[4 * j + 1];
-                a.z = pre + v[4 * j + 2];
-                a.w = pre + v[4 * j + 3];
-                st[stage_slot<S>(t * S + j)] = a;
-            }
-            __syncthreads();
-            u32x4* yv = reinterpret_cast<u32x4*>(y + tbase);
-#pragma unroll
-            for (int q = 0; q < S; ++q) __builtin_nontemporal_store(st[stage_slot<S>(q * B + t)], yv + q * B + t);
-            return;
-        }
-    }
 #pragma unroll
     for (int k = 0; k < I; ++k)
         if (base + k < n) y[base + k] = (int32_t)(pre + v[k]);

@@ -415,7 +415,7 @@ MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_mode
 
 def load_default():
     """The cost model shipped with the package (trained on MI355X by
-    `python -m paper_2206_07896_amd.learned`), or None."""
+    `python -m paper_2206_07896_amd.train`), or None."""
     if not os.path.exists(MODEL_PATH):
         return None
     with open(MODEL_PATH) as f:
