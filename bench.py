@@ -1,7 +1,7 @@
 """Benchmark of the SPMD kernel-grid executor on one MI355X.
 
 One step = one pass of the warp-primitive workload through the C ABI:
-  * SCAN_I32 over 2^26 int32 uniform in [0, 100], blockDim 512 (32 items
+  * SCAN_I32 over 2^26 int32 uniform in [0, 100], blockDim 512 (64 items
     per thread, single pass with decoupled look-back), then
   * HIST256_U32 over 2^27 uint32 keys drawn Zipf(1.1) over 256 bins with
     per-block LDS sub-histograms.
@@ -36,7 +36,7 @@ FP32_MFMA_PEAK_TFS = 157.3     # MI355X dense fp32 matrix
 
 SCAN_N = 1 << 26
 HIST_N = 1 << 27
-SCAN_BLOCK, SCAN_ITEMS = 512, 32
+SCAN_BLOCK, SCAN_ITEMS = 512, 64
 HIST_GRID, HIST_BLOCK = 256, 1024
 
 

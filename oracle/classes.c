@@ -190,8 +190,8 @@ int oracle_reduce_i32(const int32_t *x, uint32_t n, uint32_t grid, uint32_t bloc
 /* A single-pass GPU scan computes the same numbers because addition mod  */
 /* 2^32 is associative and commutative.                                    */
 /* ===================================================================== */
-#define SC_MAXITEMS 32
-/* registers: items 0..31, thread total, shuffle result, width, the value
+#define SC_MAXITEMS 64
+/* registers: items 0..63, thread total, shuffle result, width, the value
  * being warp-scanned by the current warp region (SC_INCL for the thread
  * totals, SC_W0 for warp 0's scan of the warp totals), deltas 1..16 */
 enum { SC_TOT = SC_MAXITEMS, SC_TMP, SC_WID, SC_INCL, SC_W0, SC_D0, SC_NREG = SC_D0 + 5 };

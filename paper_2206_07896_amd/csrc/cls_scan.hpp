@@ -45,12 +45,20 @@ struct ScanLds {
 
 // Exclusive carry of `tile`, computed by wave 0 (the 64 lanes call it).
 // Polling is the costly part on gfx950: every status read is a device-
-// coherent access, and many tiles poll the same few lines.  So the wave
-// first polls only the immediate predecessor (one address for all lanes,
-// exponential back-off) until it has published; older predecessors have
-// almost always published by then.  It then reads 64 predecessors at a
-// time, waits (with back-off) for any lane still unwritten, keeps the words
-// up to the nearest inclusive prefix, and moves back 64 if there is none.
+// coherent access that leaves the XCD, about half a microsecond.  So the
+// wave first polls only the immediate predecessor (one address for all
+// lanes, exponential back-off) until it has published; older predecessors
+// have almost always published by then.  It then reads a window of
+// LOOKBACK_WINDOW predecessors in one round trip (each lane LOOKBACK_PER_LANE
+// words, predecessor tile - 1 - (lane + 64 j) in slot j), waits for any word
+// that is unpublished and nearer than the nearest inclusive prefix, sums
+// the words up to that prefix, and moves back a whole window if there is
+// none.  A tile deep in a batch of concurrently running tiles then finds
+// an inclusive prefix hundreds of tiles back in one step instead of one
+// step per 64 tiles.
+constexpr int LOOKBACK_PER_LANE = 2;
+constexpr int LOOKBACK_WINDOW = 64 * LOOKBACK_PER_LANE;
+
 __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t tile, uint32_t agg, uint32_t tag,
                                                   uint32_t* err) {
     const uint32_t lane = lane64();
@@ -66,39 +74,73 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
         nap = nap < 16u ? nap * 2u : 16u;
     }
     uint32_t excl = 0;
-    int64_t pos = (int64_t)tile - 1;
+    int64_t pos = (int64_t)tile - 1;  // nearest predecessor of this window
     for (;;) {
-        const int64_t idx = pos - (int64_t)lane;
-        uint64_t s = 0;
-        uint32_t f = SCAN_INCL;  // before tile 0: a zero prefix
+        uint32_t val[LOOKBACK_PER_LANE], flg[LOOKBACK_PER_LANE];
+#pragma unroll
+        for (int j = 0; j < LOOKBACK_PER_LANE; ++j) {
+            const int64_t idx = pos - (int64_t)lane - 64 * j;
+            uint64_t w = 0;
+            uint32_t f = SCAN_INCL;  // before tile 0: a zero prefix
+            if (idx >= 0) {
+                w = status_get(status + idx);
+                f = status_flag(w, tag);
+            }
+            val[j] = (uint32_t)(w >> 32);
+            flg[j] = f;
+        }
+        int jstar = LOOKBACK_PER_LANE;  // slot of the nearest inclusive prefix
+        uint32_t kstar = 64;             // its lane
         spins = 0;
         nap = 1;
         for (;;) {
-            if (idx >= 0) {
-                s = status_get(status + idx);
-                f = status_flag(s, tag);
+            jstar = LOOKBACK_PER_LANE;
+            kstar = 64;
+#pragma unroll
+            for (int j = LOOKBACK_PER_LANE - 1; j >= 0; --j) {
+                const uint64_t inc = __builtin_amdgcn_ballot_w64(flg[j] == SCAN_INCL);
+                if (inc) {
+                    jstar = j;
+                    kstar = (uint32_t)__builtin_ctzll(inc);
+                }
             }
-            if (__builtin_amdgcn_ballot_w64(f == 0u) == 0) break;
+            // anything unpublished nearer than the inclusive prefix?
+            bool missing = false;
+#pragma unroll
+            for (int j = 0; j < LOOKBACK_PER_LANE; ++j) {
+                const bool nearer = j < jstar || (j == jstar && lane < kstar);
+                if (__builtin_amdgcn_ballot_w64(nearer && flg[j] == 0u)) missing = true;
+            }
+            if (!missing) break;
             if (++spins >= LOOKBACK_SPIN_LIMIT) {
                 if (lane == 0) atomicOr(err, ERRBIT_SPIN_LIMIT);
-                if (f == 0u) {
-                    s = 0;
-                    f = SCAN_INCL;
-                }
+#pragma unroll
+                for (int j = 0; j < LOOKBACK_PER_LANE; ++j)
+                    if (flg[j] == 0u) {
+                        val[j] = 0;
+                        flg[j] = SCAN_AGG;
+                    }
                 break;
             }
             backoff_sleep(nap);
             nap = nap < 16u ? nap * 2u : 16u;
+#pragma unroll
+            for (int j = 0; j < LOOKBACK_PER_LANE; ++j) {
+                const int64_t idx = pos - (int64_t)lane - 64 * j;
+                if (flg[j] == 0u && idx >= 0) {
+                    const uint64_t w = status_get(status + idx);
+                    val[j] = (uint32_t)(w >> 32);
+                    flg[j] = status_flag(w, tag);
+                }
+            }
         }
-        const uint64_t incl = __builtin_amdgcn_ballot_w64(f == SCAN_INCL);
-        const uint32_t val = (uint32_t)(s >> 32);
-        if (incl) {
-            const uint32_t k = (uint32_t)__builtin_ctzll(incl);  // nearest inclusive predecessor
-            excl += wave_sum(lane <= k ? val : 0u);
-            break;
-        }
-        excl += wave_sum(val);
-        pos -= 64;
+        uint32_t part = 0;
+#pragma unroll
+        for (int j = 0; j < LOOKBACK_PER_LANE; ++j)
+            if (j < jstar || (j == jstar && lane <= kstar)) part += val[j];
+        excl += wave_sum(part);
+        if (jstar < LOOKBACK_PER_LANE) break;
+        pos -= LOOKBACK_WINDOW;
     }
     if (lane == 0) status_put(status + tile, status_pack(excl + agg, SCAN_INCL, tag));
     return excl;

@@ -46,6 +46,9 @@ static void launch_b(uint32_t I, dim3 g, size_t dyn, hipStream_t s, const int32_
     case 8: hipLaunchKernelGGL((scan_i32_kernel<B, 8>), g, b, dyn, s, x, y, n, ws, err, vec); break;
     case 16: hipLaunchKernelGGL((scan_i32_kernel<B, 16>), g, b, dyn, s, x, y, n, ws, err, vec); break;
     case 32: hipLaunchKernelGGL((scan_i32_kernel<B, 32>), g, b, dyn, s, x, y, n, ws, err, vec); break;
+    case 64:
+        if constexpr (B <= 512) hipLaunchKernelGGL((scan_i32_kernel<B, 64>), g, b, dyn, s, x, y, n, ws, err, vec);
+        break;
     }
 }
 
@@ -61,7 +64,7 @@ int launch_scan_i32(const LaunchCtx& c) {
     if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
     const uint64_t per = ((uint64_t)n + (uint64_t)c.grid.x * B - 1) / ((uint64_t)c.grid.x * B);
     const uint32_t I = next_pow2(per ? (uint32_t)per : 1u);
-    if (I > 32) return SPMD_ERR_INVALID_DIM;
+    if (I > 64 || (I == 64 && B > 512)) return SPMD_ERR_INVALID_DIM;
     if (n == 0) return SPMD_OK;
     const bool vec = aligned(x, 16) && aligned(y, 16);
     const uint32_t G = c.grid.x;

@@ -112,7 +112,8 @@ def test_reduce_wrapping_and_unaligned(spmd):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,block,items", [(1, 64, 1), (100, 64, 1), (5000, 64, 4), (8193, 128, 8), (70001, 512, 16),
-                                           (200000, 1024, 32), (123457, 256, 2)])
+                                           (200000, 1024, 32), (123457, 256, 2), (300001, 512, 64),
+                                           (65536 * 3 + 17, 256, 64), (40000, 512, 32)])
 def test_scan(spmd, n, block, items):
     say("scan", n, block, items)
     x = synth.uniform_int32(synth.SEED_SCAN + n, n, -(2**31), 2**31 - 1)

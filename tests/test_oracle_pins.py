@@ -174,7 +174,7 @@ def _check_scan_invariant(x, y):
 
 
 @pytest.mark.parametrize("n,block,items", [(1, 32, 1), (33, 32, 1), (1000, 64, 4), (8191, 128, 3),
-                                           (100000, 512, 16), (70000, 96, 7)])
+                                           (100000, 512, 16), (70000, 96, 7), (70001, 512, 64)])
 def test_scan_invariant_and_all_ones(n, block, items):
     x = synth.uniform_int32(n, n, 0, 100)
     y = oracle.scan_i32(x, block=block, items=items)
