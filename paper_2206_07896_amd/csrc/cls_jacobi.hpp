@@ -10,6 +10,7 @@
 // outside the grid are staged as zero and never read.
 #pragma once
 #include "common.hpp"
+#include "warp32.hpp"
 
 namespace spmd {
 
@@ -71,6 +72,94 @@ __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float*
             out = 0.25f * sum;
         }
         v[gy * NX + gx] = out;
+    }
+}
+
+
+// Vector form, for nx a multiple of 4 and 16-byte aligned rows: a workgroup
+// of 64 x BY threads owns 256 columns and BY*C rows, each thread four
+// consecutive columns (one 16-byte load or store per row) and C rows, BY
+// rows apart.  The interior sits at LDS column 4 so that every row of four
+// is 16-byte aligned; the halo columns sit at 3 and 260.  Each cell is
+// computed exactly as in jacobi_block.
+constexpr int JV_W = 256, JV_LD = JV_W + 8;
+
+template <int BY, int C>
+struct JacobiV4Lds {
+    alignas(16) float t[BY * C + 2][JV_LD];
+};
+
+template <int BY, int C>
+__device__ __forceinline__ void jacobi_block_v4(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
+                                                uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
+                                                JacobiV4Lds<BY, C>& L) {
+#pragma clang fp contract(off)
+    constexpr int TY = BY * C;
+    constexpr int H = TY + 2;
+    constexpr int NP = (H + BY - 1) / BY;
+    const int64_t x0 = (int64_t)bx * JV_W, y0 = (int64_t)by * TY;
+    const int64_t NX = nx, NY = ny;
+    const int64_t gx0 = x0 + 4 * tx;                 // first of this thread's four columns
+    const int64_t gxh = tx == 0 ? x0 - 1 : x0 + JV_W;  // halo column (threads tx < 2)
+    const bool has_c = gx0 < NX;                     // then all four are (NX % 4 == 0)
+    const bool has_h = tx < 2 && gxh >= 0 && gxh < NX;
+    f32x4 vc[NP];
+    float vh[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
+        const int64_t gy = y0 - 1 + r;
+        const bool rowok = r < H && gy >= 0 && gy < NY;
+        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        vc[p] = (rowok && has_c) ? *reinterpret_cast<const f32x4*>(u + gy * NX + gx0) : z;
+        vh[p] = (rowok && has_h) ? u[gy * NX + gxh] : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
+        if (r < H) {
+            *reinterpret_cast<f32x4*>(&L.t[r][4 + 4 * tx]) = vc[p];
+            if (tx < 2) L.t[r][tx == 0 ? 3 : 4 + JV_W] = vh[p];
+        }
+    }
+    __syncthreads();
+    if (!has_c) return;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int r = ty + k * BY;
+        const int64_t gy = y0 + r;
+        if (gy >= NY) break;
+        const f32x4 c = *reinterpret_cast<const f32x4*>(&L.t[r + 1][4 + 4 * tx]);
+        f32x4 out = c;
+        if (gy != 0 && gy != NY - 1) {
+            const f32x4 n = *reinterpret_cast<const f32x4*>(&L.t[r][4 + 4 * tx]);
+            const f32x4 s = *reinterpret_cast<const f32x4*>(&L.t[r + 2][4 + 4 * tx]);
+            const float wl = L.t[r + 1][3 + 4 * tx];
+            const float er = L.t[r + 1][8 + 4 * tx];
+            const float w[4] = {wl, c.x, c.y, c.z};
+            const float e[4] = {c.y, c.z, c.w, er};
+            const float nn[4] = {n.x, n.y, n.z, n.w};
+            const float ss[4] = {s.x, s.y, s.z, s.w};
+            const float cc[4] = {c.x, c.y, c.z, c.w};
+            float o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gx = gx0 + j;
+                if (gx == 0 || gx == NX - 1) {
+                    o[j] = cc[j];
+                } else {
+                    const float ns = nn[j] + ss[j];
+                    const float we = w[j] + e[j];
+                    const float sum = ns + we;
+                    o[j] = 0.25f * sum;
+                }
+            }
+            out.x = o[0];
+            out.y = o[1];
+            out.z = o[2];
+            out.w = o[3];
+        }
+        *reinterpret_cast<f32x4*>(v + gy * NX + gx0) = out;
     }
 }
 

@@ -10,6 +10,13 @@ __global__ __launch_bounds__(BX* BY) void jacobi5_kernel(const float* __restrict
     jacobi_block<BX, BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, L);
 }
 
+template <int BY, int C>
+__global__ __launch_bounds__(64 * BY) void jacobi5_v4_kernel(const float* __restrict__ u, float* __restrict__ v,
+                                                             uint32_t nx, uint32_t ny) {
+    __shared__ JacobiV4Lds<BY, C> L;
+    jacobi_block_v4<BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, L);
+}
+
 template <int BX, int BY>
 static void launch_c(uint32_t C, dim3 g, size_t dyn, hipStream_t s, const float* u, float* v, uint32_t nx,
                      uint32_t ny) {
@@ -38,6 +45,25 @@ int launch_jacobi5_f32(const LaunchCtx& c) {
     if (C > 16) return SPMD_ERR_INVALID_DIM;
     dim3 g(c.grid.x, c.grid.y);
     const size_t d = c.dyn_shmem;
+    const uint64_t brow = (uint64_t)BY * C;  // rows of one block row of the launch
+    if (nx % 4u == 0 && aligned(u, 16) && aligned(v, 16) && brow >= 4 && brow <= 64) {
+        // The blocks of one block row are fetched 256 columns at a time
+        // (coarse-grained fetching along x, Section IV-A) and run as one
+        // workgroup of 64 x 4 threads, four columns per thread: 16-byte
+        // loads and stores, the same rows as the launch's blocks, every
+        // cell computed as in its own block.
+        const dim3 gv((nx + JV_W - 1) / JV_W, c.grid.y), bv(64, 4);
+        hipStream_t st = c.stream;
+        switch (brow) {
+        case 4: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny); break;
+        case 8: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny); break;
+        case 16: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny); break;
+        case 32: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny); break;
+        case 64: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny); break;
+        }
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? SPMD_OK : hip_fail(e);
+    }
     if (BX == 16 && BY == 16 && C <= 4) {
         // Four consecutive logical blocks along x per workgroup (the
         // coarse-grained fetch of Section IV-A, 4 blocks per fetch): their

@@ -183,7 +183,8 @@ SHAPES = [(16, 16), (32, 8), (64, 4), (64, 8), (128, 2), (128, 4), (256, 1)]
 @pytest.mark.parametrize("block", SHAPES)
 @pytest.mark.parametrize("cells", [1, 4])
 def test_jacobi_one_sweep(spmd, block, cells):
-    for (ny, nx) in [(33, 70), (130, 257), (3, 3)]:
+    # nx % 4 == 0 takes the 16-byte (four columns per thread) form, the rest the scalar one
+    for (ny, nx) in [(33, 70), (130, 257), (3, 3), (33, 68), (130, 520), (5, 4), (64, 260)]:
         say("jacobi", ny, nx, block, cells)
         u = synth.uniform_f32(synth.SEED_JACOBI + nx, ny * nx).reshape(ny, nx)
         want = oracle.jacobi5_f32(u, 16, 16)
@@ -192,8 +193,9 @@ def test_jacobi_one_sweep(spmd, block, cells):
         assert np.array_equal(got, want)
 
 
-def test_jacobi_sweeps_bit_exact(spmd):
-    ny, nx = 300, 517
+@pytest.mark.parametrize("nx", [517, 516])
+def test_jacobi_sweeps_bit_exact(spmd, nx):
+    ny = 300
     say("jacobi 25 sweeps", ny, nx)
     u = synth.uniform_f32(5, ny * nx).reshape(ny, nx)
     got = host(spmd.ops.jacobi5_sweeps(dev(u), 25, block=(64, 4), cells=4))
