@@ -110,12 +110,14 @@ def main():
                          "(500 training launches; minutes of GPU time)")
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
+    ap.add_argument("--only-gemm", action="store_true",
+                    help="run only the 4096^3 fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
     args = ap.parse_args()
     if args.only_step:
         args.no_cpu = args.no_extra = args.no_mixed = True
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(each kernel class would shard over GPUs as described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (each kernel class "
+              "would shard over GPUs with at most one collective exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -125,6 +127,9 @@ def main():
 
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
+    if args.only_gemm:
+        print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5)}), flush=True)
+        return
 
     log("generating inputs")
     xs_h = synth.uniform_int32(synth.SEED_SCAN, SCAN_N, 0, 100)
@@ -338,14 +343,22 @@ def extra_workloads(spmd, synth):
             "us": round(ms * 1e3, 2), "GB/s": round(byt / ms / 1e6, 1),
             "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
     del u, a, bb
-    # GEMM 4096^3 fp32
+    res.update(gemm_workloads(spmd, synth))
+    return res
+
+
+def gemm_workloads(spmd, synth, reps=10):
+    """C = A B, 4096^3 fp32 N(0,1), at the configured 64 x 64 tiles and at 128 x 128."""
+    import torch
+
+    res = {}
     n = 4096
     A = to_dev(synth.normal_f32(synth.SEED_GEMM, n * n).reshape(n, n))
     B = to_dev(synth.normal_f32(synth.SEED_GEMM + 1, n * n).reshape(n, n))
     C = torch.empty_like(A)
     for tile in (64, 128):
         log(f"gemm tile {tile}")
-        ms = measure(lambda: spmd.ops.gemm_f32(A, B, C, tile), 10)
+        ms = measure(lambda: spmd.ops.gemm_f32(A, B, C, tile), reps)
         tf = 2 * n**3 / (ms * 1e-3) / 1e12
         res[f"gemm_f32 4096^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
                                               "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
@@ -387,6 +400,25 @@ def mixed_queue(spmd, count, reps=10):
     t_graph = measure(b.graph_launch, reps, warmup=2)
     t_each = measure(b.launch_each, max(3, reps // 2), warmup=1)
     spmd.sync()
+    # the same one-launch-per-instance sequence captured once into a graph:
+    # the dispatch cost of separate grids without the host's launch cost
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.launch_each()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    each_graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(each_graph):
+        b.launch_each()
+    for _ in range(2):  # every replay gives the eager result
+        data.outputs.fill_(-1)
+        each_graph.replay()
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(ref, data.outputs))
+    t_each_graph = measure(each_graph.replay, 5, warmup=1)
+    del each_graph
+    spmd.sync()
     b.close()
     gbytes = data.total_bytes / 1e9
     res = {
@@ -395,6 +427,7 @@ def mixed_queue(spmd, count, reps=10):
         "kernel_launches_one_by_one": st["each_launches"],
         "ms_one_by_one": round(t_each, 3),
         "launches_per_s_one_by_one": round(count / (t_each * 1e-3), 1),
+        "ms_one_by_one_captured_graph": round(t_each_graph, 3),
         "heuristic": {"schedule": "blockDim as launched, 4 items/thread, average coarse-grained fetching "
                                   "ceil(blocks/pool)",
                       "chunks": st["chunks"], "kernel_launches": st["persistent_launches"],
@@ -403,7 +436,7 @@ def mixed_queue(spmd, count, reps=10):
                       "speedup_vs_one_by_one": round(t_each / t_graph, 3),
                       "GB/s": round(gbytes / (t_graph * 1e-3), 1)},
     }
-    log(f"mixed: one-by-one {t_each:.2f} ms, heuristic graph {t_graph:.2f} ms")
+    log(f"mixed: one-by-one {t_each:.2f} ms (captured {t_each_graph:.2f} ms), heuristic graph {t_graph:.2f} ms")
     model = L.load_default()
     if model is not None:
         choice, _, sd = model.choose(specs)
@@ -422,6 +455,7 @@ def mixed_queue(spmd, count, reps=10):
                           "ms_graph": round(t_l, 3),
                           "launches_per_s": round(count / (t_l * 1e-3), 1),
                           "speedup_vs_one_by_one": round(t_each / t_l, 3),
+                          "speedup_vs_one_by_one_captured_graph": round(t_each_graph / t_l, 3),
                           "speedup_vs_heuristic": round(t_graph / t_l, 3),
                           "GB/s": round(gbytes / (t_l * 1e-3), 1),
                           "frac_hbm": round(gbytes / (t_l * 1e-3) / HBM_PEAK_GBS, 4),

@@ -194,7 +194,7 @@ def test_choose_matches_oracle(L, k, c):
                                        mu.astype(np.float64), inv_sd.astype(np.float64))
     assert best[5] == 0xFFFFFFFF and ob[5] == -1
     assert best[6] == c - 1
-    # the oracle's mean over every (launch, candidate), to judge near-ties
+    # the oracle's mean over every (launch, candidate), to recognise near-ties
     X = np.concatenate([np.repeat(feats, c, axis=0), np.tile(cands, (m, 1))], axis=1)
     means = np.mean([omlp.forward(q.astype(np.float64), X, mu.astype(np.float64), inv_sd.astype(np.float64))[0]
                      for q in params], axis=0).reshape(m, c)
