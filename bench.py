@@ -363,6 +363,12 @@ def gemm_workloads(spmd, synth, reps=10):
         res[f"gemm_f32 4096^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
                                               "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
     spmd.sync()
+    # reference only: the vendor library GEMM (torch.matmul, fp32 without TF32) on the same operands
+    torch.backends.cuda.matmul.allow_tf32 = False
+    ms = measure(lambda: torch.matmul(A, B, out=C), reps)
+    tf = 2 * n**3 / (ms * 1e-3) / 1e12
+    res["reference: torch.matmul fp32 4096^3"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
+                                                  "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
     return res
 
 

@@ -40,6 +40,7 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A, const fl
     constexpr int RT = T / 64;           // 32 x 32 tiles per wave edge
     constexpr int WT = T / 2;            // wave tile edge
     constexpr int PT = T * KT / 1024;    // float4 loads per thread per operand
+    constexpr int KQ = KT / 4;           // float4 per row of an A slice
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -55,39 +56,48 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A, const fl
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     f32x4 ra[PT], rb[PT];
+    // Interior slices (the whole T x KT and KT x T slices inside the
+    // matrices, rows 16-byte aligned) are decided once per block and slice,
+    // so their loads issue back to back with no per-thread branches; edge
+    // slices take the element-wise path.
+    const bool inner_mn = vecA && vecB && m0 + T <= Mi && n0 + T <= Ni;
     auto gload = [&](int kt) {
         const int64_t k0 = (int64_t)kt * KT;
-        const bool fullk = k0 + KT <= Ki;
+        if (inner_mn && k0 + KT <= Ki) {
+#pragma unroll
+            for (int j = 0; j < PT; ++j) {
+                const int q = tid + 256 * j;
+                ra[j] = *reinterpret_cast<const f32x4*>(A + (m0 + q / KQ) * Ki + k0 + (q % KQ) * 4);
+            }
+#pragma unroll
+            for (int j = 0; j < PT; ++j) {
+                const int q = tid + 256 * j;
+                rb[j] = *reinterpret_cast<const f32x4*>(B + (k0 + q / (T / 4)) * Ni + n0 + (q % (T / 4)) * 4);
+            }
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
-            const int q = tid + 256 * j;  // A slice: T rows x 4 float4
-            const int row = q >> 2, kq = (q & 3) * 4;
+            const int q = tid + 256 * j;  // A slice: T rows x KT/4 float4
+            const int row = q / KQ, kq = (q % KQ) * 4;
             const int64_t gm = m0 + row, gk = k0 + kq;
-            if (vecA && fullk && gm < Mi) {
-                ra[j] = *reinterpret_cast<const f32x4*>(A + gm * Ki + gk);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) ra[j][e] = (gm < Mi && gk + e < Ki) ? A[gm * Ki + gk + e] : 0.0f;
-            }
+            for (int e = 0; e < 4; ++e) ra[j][e] = (gm < Mi && gk + e < Ki) ? A[gm * Ki + gk + e] : 0.0f;
         }
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
             const int q = tid + 256 * j;  // B slice: KT rows x T/4 float4
             const int row = q / (T / 4), c4 = (q % (T / 4)) * 4;
             const int64_t gk = k0 + row, gn = n0 + c4;
-            if (vecB && gk < Ki && gn + 4 <= Ni) {
-                rb[j] = *reinterpret_cast<const f32x4*>(B + gk * Ni + gn);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) rb[j][e] = (gk < Ki && gn + e < Ni) ? B[gk * Ni + gn + e] : 0.0f;
-            }
+            for (int e = 0; e < 4; ++e) rb[j][e] = (gk < Ki && gn + e < Ni) ? B[gk * Ni + gn + e] : 0.0f;
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
             const int q = tid + 256 * j;
-            const int row = q >> 2, kq = (q & 3) * 4;
+            const int row = q / KQ, kq = (q % KQ) * 4;
 #pragma unroll
             for (int e = 0; e < 4; ++e) L.a[buf][kq + e][row] = ra[j][e];
         }
