@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "cls_hist.hpp"
@@ -246,6 +247,10 @@ struct spmd_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // fork/join of the group kernels over side streams (two or more groups)
+    int ngroups_active = 0;
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[NGROUPS] = {};
 };
 
 namespace {
@@ -411,6 +416,29 @@ void launch_group(uint32_t block, dim3 gr, hipStream_t s, const BatchDesc* descs
     }
 }
 
+// Side streams for the group kernels, per device, created once with the
+// device current and kept for the life of the process (default priority).
+// A run forks them from the caller's stream with an event and joins them
+// back with one event per group, so runs on one stream stay ordered and a
+// captured run becomes a graph with one branch per group.
+std::mutex g_side_mu;
+hipStream_t g_side[64][NGROUPS];
+bool g_side_ready[64];
+
+int side_streams(const DevInfo* di, hipStream_t** out) {
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (di->device < 0 || di->device >= 64) return SPMD_ERR_HIP;
+    if (!g_side_ready[di->device]) {
+        for (int g = 0; g < NGROUPS; ++g) {
+            hipError_t e = hipStreamCreateWithFlags(&g_side[di->device][g], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        g_side_ready[di->device] = true;
+    }
+    *out = g_side[di->device];
+    return SPMD_OK;
+}
+
 int enqueue_run(spmd_batch* b, hipStream_t s) {
     clear_stale_error();
     const uint64_t run_words = b->run_bytes / 16;
@@ -420,24 +448,56 @@ int enqueue_run(spmd_batch* b, hipStream_t s) {
                        reinterpret_cast<uint32_t* const*>(b->ws + b->hist_off), b->nhist);
     const BatchDesc* descs = reinterpret_cast<const BatchDesc*>(b->ws + b->desc_off);
     uint32_t* err = b->dev->err_word;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    const bool fork = b->ngroups_active >= 2 && b->ev_fork != nullptr;
+    hipStream_t* side = nullptr;
+    if (fork) {
+        int rc = side_streams(b->dev, &side);
+        if (rc) return rc;
+        if ((e = hipEventRecord(b->ev_fork, s)) != hipSuccess) return hip_fail(e);
+    }
+    int k = 0;
     for (int g = 0; g < NGROUPS; ++g) {
         if (!b->chunks[g]) continue;
+        hipStream_t gs = s;
+        if (fork) {
+            gs = side[k];
+            if ((e = hipStreamWaitEvent(gs, b->ev_fork, 0)) != hipSuccess) return hip_fail(e);
+        }
         const uint32_t* cmap = reinterpret_cast<const uint32_t*>(b->ws + b->chunk_off[g]);
         uint32_t* cursor = reinterpret_cast<uint32_t*>(b->ws + 64 * g);
         const uint32_t block = SIZE_B[g % NSIZES];
         const dim3 gr(b->grid[g]);
         switch (CLS_ID[g / NSIZES]) {
-        case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, s, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
+        case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
         }
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+        if (fork) {
+            if ((e = hipEventRecord(b->ev_join[k], gs)) != hipSuccess) return hip_fail(e);
+            if ((e = hipStreamWaitEvent(s, b->ev_join[k], 0)) != hipSuccess) return hip_fail(e);
+        }
+        ++k;
     }
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+    return SPMD_OK;
 }
 
 }  // namespace
+
+// For plans destroyed right after one enqueue (spmd_launch_batch): run the
+// group kernels in order on the caller's stream, so no event outlives its
+// plan while the GPU still has to reach it.
+void spmd::batch_run_in_order(spmd_batch* b) {
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    for (int g = 0; g < NGROUPS; ++g)
+        if (b->ev_join[g]) hipEventDestroy(b->ev_join[g]);
+    b->ev_fork = nullptr;
+    for (int g = 0; g < NGROUPS; ++g) b->ev_join[g] = nullptr;
+    b->ngroups_active = 1;
+}
 
 extern "C" {
 
@@ -548,6 +608,16 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
             return rc;
         }
         b->grid[g] = (uint32_t)std::min<uint64_t>(pool, b->chunks[g]);
+        ++b->ngroups_active;
+    }
+    if (b->ngroups_active >= 2) {
+        e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        for (int k = 0; k < b->ngroups_active && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            spmd_batch_destroy(b);
+            return hip_fail(e);
+        }
     }
     *out = b;
     return SPMD_OK;
@@ -646,6 +716,9 @@ int spmd_batch_destroy(spmd_batch* b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    if (b->ev_fork) hipEventDestroy(b->ev_fork);
+    for (int g = 0; g < NGROUPS; ++g)
+        if (b->ev_join[g]) hipEventDestroy(b->ev_join[g]);
     delete b;
     return SPMD_OK;
 }

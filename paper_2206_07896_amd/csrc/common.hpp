@@ -76,6 +76,14 @@ int launch_warptest(const LaunchCtx& c);
 int launch_reverse_i32(const LaunchCtx& c);
 
 size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
+
+}  // namespace spmd
+
+struct spmd_batch;
+namespace spmd {
+// Batch plans that are enqueued once and destroyed at once run their group
+// kernels in order on the caller's stream (batch.hip).
+void batch_run_in_order(spmd_batch* b);
 size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
 
 }  // namespace spmd

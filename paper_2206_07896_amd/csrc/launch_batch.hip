@@ -316,6 +316,7 @@ int spmd_launch_batch(const spmd_launch_desc* descs, int n, int mode, void* work
     }
     spmd_batch* b = nullptr;
     if ((rc = spmd_batch_create(items.data(), sched.data(), n, workspace, ws_bytes, 0, &b))) return rc;
+    batch_run_in_order(b);
     rc = spmd_batch_launch(b, stream);
     spmd_batch_destroy(b);  // host plan only: the device tables stay in the workspace
     if (rc == SPMD_OK) g_report = rep;

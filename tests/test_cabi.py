@@ -213,3 +213,56 @@ def test_launch_batch_rejects_unbatchable_launches(spmd):
     # learned mode without a model, bad mode, missing workspace: errors, no device work
     assert lib.spmd_launch_batch(one, 1, 7, None, 0, None) == -4
     assert lib.spmd_launch_batch(one, 1, 0, None, 0, None) == -8
+
+
+def test_launch_batch_workspace_covers_every_schedule(spmd):
+    """The bound spmd_launch_batch reserves must hold the plan of any
+    schedule the cost model may pick: for a seeded mix of launches and for
+    every candidate applied to all of them, the plan fits."""
+    import ctypes as C
+
+    from paper_2206_07896_amd import batch as B
+
+    rng = np.random.default_rng(3)
+    cands = B.sched_candidates()
+    keep = []
+    descs, items = [], []
+    for i in range(24):
+        kid = [spmd.REDUCE_I32, spmd.SCAN_I32, spmd.HIST256_U32, spmd.JACOBI5_F32][i % 4]
+        n = int(rng.integers(1, 1 << 20))
+        bd = int(rng.choice([32, 64, 96, 128, 256, 512, 1024]))
+        vals = [C.c_void_p(0x10000 * (i + 1)), C.c_void_p(0x10000 * (i + 1) + 0x8000)]
+        if kid == spmd.JACOBI5_F32:
+            nx = ny = max(1, int(np.sqrt(n)))
+            ints = [C.c_uint32(nx), C.c_uint32(ny)]
+            args = vals + ints
+            items.append(B.BatchItem(kid, nx, ny, bd, vals[0].value, vals[1].value))
+        else:
+            ints = [C.c_uint32(n)]
+            args = (vals[:1] + [vals[1], vals[1]] + ints + [vals[1]]) if kid == spmd.REDUCE_I32 else \
+                   (vals + ints + [vals[1]]) if kid == spmd.SCAN_I32 else (vals + ints)
+            items.append(B.BatchItem(kid, n, 1, bd, vals[0].value, vals[1].value))
+        ptrs = (C.c_void_p * len(args))(*[C.cast(C.pointer(a), C.c_void_p).value for a in args])
+        keep.append((args, ptrs))
+        descs.append(B.LaunchDesc(kid, (C.c_uint32 * 3)(4, 1, 1), (C.c_uint32 * 3)(bd, 1, 1), 0,
+                                  C.cast(ptrs, C.POINTER(C.c_void_p))))
+    lib = spmd.lib()
+    darr = (B.LaunchDesc * len(descs))(*descs)
+    bound = lib.spmd_launch_batch_workspace_size(darr, len(descs))
+    assert bound > 0
+    iarr = (B.BatchItem * len(items))(*items)
+    for c in cands:
+        sch = (B.Schedule * len(items))(*[B.Schedule(*c) for _ in items])
+        need = lib.spmd_batch_workspace_size(iarr, sch, len(items))
+        if need == 0:  # candidate invalid for a class (JACOBI items > 8)
+            assert c[1] > 8
+            continue
+        assert need <= bound, (c, need, bound)
+    # and for a random mix of per-launch schedules
+    for _ in range(50):
+        pick = [cands[int(j)] for j in rng.integers(0, len(cands), len(items))]
+        pick = [(b, min(it, 8) if items[k].kernel_id == spmd.JACOBI5_F32 else it, f)
+                for k, (b, it, f) in enumerate(pick)]
+        sch = (B.Schedule * len(items))(*[B.Schedule(*c) for c in pick])
+        need = lib.spmd_batch_workspace_size(iarr, sch, len(items))
+        assert 0 < need <= bound
