@@ -111,7 +111,10 @@ def main():
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
-                    help="run only the 4096^3 fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
+                    help="run only the fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
+    ap.add_argument("--only", choices=("reduce", "jacobi"), default=None,
+                    help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
+    ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
     if args.only_step:
         args.no_cpu = args.no_extra = args.no_mixed = True
@@ -128,7 +131,13 @@ def main():
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
     if args.only_gemm:
-        print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5)}), flush=True)
+        print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5, n=args.gemm_n)}), flush=True)
+        return
+    if args.only:
+        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads}[args.only]
+        out = fn(spmd, synth)
+        calibration_copies()
+        print(json.dumps({f"only_{args.only}": out}), flush=True)
         return
 
     log("generating inputs")
@@ -174,13 +183,7 @@ def main():
     assert int(h.astype(np.int64).sum()) == HIST_N
 
     if args.only_step:
-        # a copy of known size, for scaling hardware byte counters in profiler runs
-        src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copies()
 
     scan_bytes = 8 * SCAN_N
     hist_bytes = 4 * HIST_N + 1024
@@ -263,19 +266,49 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def calibration_copies():
+    """Three device copies of 256 MiB: a kernel of known traffic, for scaling
+    hardware byte counters in profiler runs."""
+    import torch
+
+    src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def extra_workloads(spmd, synth):
     """Per-kernel figures of the other workloads (not part of the step)."""
+    res = copy_reference()
+    res.update(reduce_workloads(spmd, synth))
+    res.update(jacobi_workloads(spmd, synth))
+    res.update(gemm_workloads(spmd, synth))
+    return res
+
+
+def copy_reference():
+    """A plain device copy of 256 MiB (read + write): reference, and the
+    known-size kernel that scales the hardware byte counters."""
     import torch
 
     res = {}
-    # reference: a plain device copy of 256 MiB (read + write)
     src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     ms = measure(lambda: dst.copy_(src), 20)
     res["reference: device copy 256 MiB (torch copy_)"] = {"us": round(ms * 1e3, 2),
                                                           "GB/s": round(8 * (1 << 26) / ms / 1e6, 1)}
     del src, dst
-    # block reduction: 2^20 int32, grid 4096, block 256, 1 KiB LDS
+    return res
+
+
+def reduce_workloads(spmd, synth):
+    """REDUCE_I32: the 2^20 configuration (grid 4096, block 256, 1 KiB LDS)
+    and the same class from 2^24 to 2^30 elements under a cold cache."""
+    import torch
+
+    res = {}
     log("reduce 2^20")
     n = 1 << 20
     x = to_dev(synth.uniform_int32(synth.SEED_REDUCE, n, -1000, 1000))
@@ -312,19 +345,36 @@ def extra_workloads(spmd, synth):
         "timing": f"one graph of {per_graph} launches, median replay / {per_graph}"}
     del graph
     del x
-    # the same class where HBM, not launch latency, decides: 2^28 (1 GiB) and 2^30 (4 GiB)
-    for lg in (28, 30):
+    # the same class where HBM, not launch latency, decides: 2^24 (64 MiB) .. 2^30 (4 GiB)
+    for lg in (24, 26, 28, 30):
         n = 1 << lg
         log(f"reduce 2^{lg}")
-        x = torch.ones(n, dtype=torch.int32, device="cuda")
-        ms = measure(lambda: spmd.ops.reduce_i32(x, 4096, 256, p, o, wsr), 10)
+        # cold cache: rotate over copies totalling more than 1 GiB (4x the 256 MB cache)
+        copies = max(1, -(-(2 << 30) // (4 * n)))
+        xs_r = [torch.ones(n, dtype=torch.int32, device="cuda") for _ in range(copies)]
+        turn = [0]
+
+        def run_reduce():
+            spmd.ops.reduce_i32(xs_r[turn[0] % copies], 4096, 256, p, o, wsr)
+            turn[0] += 1
+
+        ms = measure(run_reduce, 10)
         assert int(o.cpu()[0]) == n % 2**32 - (2**32 if n % 2**32 >= 2**31 else 0)
         b = 4 * n + 4 * 4096 + 4
         res[f"reduce_i32 2^{lg} g4096 b256"] = {"us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1),
-                                              "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
-        del x
+                                              "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                              "input_copies_rotated": copies}
+        del xs_r
         torch.cuda.empty_cache()
-    # Jacobi 8192^2, 100 sweeps
+    return res
+
+
+def jacobi_workloads(spmd, synth):
+    """JACOBI5_F32: 8192^2 fp32, 100 sweeps, with the configured 16 x 16
+    blocks and with 64 x 4 blocks of 4 cells."""
+    import torch
+
+    res = {}
     nn, sweeps = 8192, 100
     u = to_dev(synth.uniform_f32(synth.SEED_JACOBI, nn * nn).reshape(nn, nn))
     a, bb = u.clone(), torch.empty_like(u)
@@ -343,16 +393,16 @@ def extra_workloads(spmd, synth):
             "us": round(ms * 1e3, 2), "GB/s": round(byt / ms / 1e6, 1),
             "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
     del u, a, bb
-    res.update(gemm_workloads(spmd, synth))
+    torch.cuda.empty_cache()
     return res
 
 
-def gemm_workloads(spmd, synth, reps=10):
-    """C = A B, 4096^3 fp32 N(0,1), at the configured 64 x 64 tiles and at 128 x 128."""
+def gemm_workloads(spmd, synth, reps=10, n=4096):
+    """C = A B, n^3 fp32 N(0,1) (4096 by default), at the configured 64 x 64
+    tiles and at 128 x 128."""
     import torch
 
     res = {}
-    n = 4096
     A = to_dev(synth.normal_f32(synth.SEED_GEMM, n * n).reshape(n, n))
     B = to_dev(synth.normal_f32(synth.SEED_GEMM + 1, n * n).reshape(n, n))
     C = torch.empty_like(A)
@@ -360,14 +410,14 @@ def gemm_workloads(spmd, synth, reps=10):
         log(f"gemm tile {tile}")
         ms = measure(lambda: spmd.ops.gemm_f32(A, B, C, tile), reps)
         tf = 2 * n**3 / (ms * 1e-3) / 1e12
-        res[f"gemm_f32 4096^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
+        res[f"gemm_f32 {n}^3 tile{tile}"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
                                               "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
     spmd.sync()
     # reference only: the vendor library GEMM (torch.matmul, fp32 without TF32) on the same operands
     torch.backends.cuda.matmul.allow_tf32 = False
     ms = measure(lambda: torch.matmul(A, B, out=C), reps)
     tf = 2 * n**3 / (ms * 1e-3) / 1e12
-    res["reference: torch.matmul fp32 4096^3"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
+    res[f"reference: torch.matmul fp32 {n}^3"] = {"us": round(ms * 1e3, 2), "TFLOP/s": round(tf, 2),
                                                   "frac_mfma_fp32": round(tf / FP32_MFMA_PEAK_TFS, 4)}
     return res
 
