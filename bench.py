@@ -352,19 +352,30 @@ def reduce_workloads(spmd, synth):
         # cold cache: rotate over copies totalling more than 1 GiB (4x the 256 MB cache)
         copies = max(1, -(-(2 << 30) // (4 * n)))
         xs_r = [torch.ones(n, dtype=torch.int32, device="cuda") for _ in range(copies)]
-        turn = [0]
-
-        def run_reduce():
-            spmd.ops.reduce_i32(xs_r[turn[0] % copies], 4096, 256, p, o, wsr)
-            turn[0] += 1
-
-        ms = measure(run_reduce, 10)
-        assert int(o.cpu()[0]) == n % 2**32 - (2**32 if n % 2**32 >= 2**31 else 0)
+        # one launch per copy in a captured graph (at least 8): device time only
+        per_graph = max(8, copies)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            spmd.ops.reduce_i32(xs_r[0], 4096, 256, p, o, wsr)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for k in range(per_graph):
+                spmd.ops.reduce_i32(xs_r[k % copies], 4096, 256, p, o, wsr)
+        ms = measure(graph.replay, 5, warmup=1) / per_graph
+        want = n % 2**32 - (2**32 if n % 2**32 >= 2**31 else 0)
+        o.fill_(0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(o.cpu()[0]) == want
         b = 4 * n + 4 * 4096 + 4
         res[f"reduce_i32 2^{lg} g4096 b256"] = {"us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1),
                                               "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
-                                              "input_copies_rotated": copies}
-        del xs_r
+                                              "input_copies_rotated": copies,
+                                              "timing": f"graph of {per_graph} launches, median replay / {per_graph}"}
+        del graph, xs_r
         torch.cuda.empty_cache()
     return res
 
