@@ -40,7 +40,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mpmd.c", "classes.c", "fp64.c"]
+_SOURCES = ["mpmd.c", "classes.c", "fp64.c", "select.c"]
 _lock = threading.Lock()
 _lib = None
 
@@ -97,6 +97,7 @@ def _load():
                 "oracle_jacobi5_f32_sweeps": [P, U32, U32, U32, P],
                 "oracle_gemm_f64": [P, P, U32, U32, U32, P],
                 "oracle_gemm_f64_entries": [P, P, U32, U32, P, P, U64, P],
+                "oracle_compact_i32": [P, U64, ctypes.c_int32, P, P],
             }
             for name, args in sig.items():
                 f = getattr(lib, name)
@@ -249,6 +250,16 @@ def gemm_f64_entries(A, B, ii, jj) -> np.ndarray:
     out = np.zeros(ii.size, np.float64)
     lib.oracle_gemm_f64_entries(_p(A), _p(B), N, K, _p(ii), _p(jj), ii.size, _p(out))
     return out
+
+
+def compact_i32(x, t: int):
+    """The elements of x greater than t, in order (select.c)."""
+    lib = _load()
+    x = _c(x, np.int32)
+    y = np.empty(max(1, x.size), np.int32)
+    m = ctypes.c_uint64(0)
+    lib.oracle_compact_i32(_p(x), x.size, int(t), _p(y), ctypes.byref(m))
+    return y[: m.value].copy()
 
 
 WARPTEST_NCASES = None

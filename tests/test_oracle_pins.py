@@ -505,3 +505,31 @@ def test_warp_order_invariance():
     ref = _run_warp(val, pred, 2, 128)
     for seed in SEEDS[:3]:
         assert np.array_equal(_run_warp(val, pred, 2, 128, seed=seed), ref)
+
+
+# --------------------------------------------------------------------------
+# COMPACT_I32: the plain definition, pinned by a list comprehension on small
+# inputs, the extreme thresholds, and order and count identities.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,t", [(0, 0), (1, 0), (37, -5), (1000, 0), (4097, 900), (4097, -1001)])
+def test_compact_brute_force(n, t):
+    x = synth.uniform_int32(0xC0 + n, n, -1000, 1000)
+    want = [int(v) for v in x if int(v) > t]
+    got = oracle.compact_i32(x, t)
+    assert got.dtype == np.int32 and got.tolist() == want
+
+
+def test_compact_extreme_thresholds_and_identities():
+    x = synth.uniform_int32(0xC1C, 1 << 16, -(2**31), 2**31 - 1)
+    x[:3] = [-(2**31), 2**31 - 1, 0]
+    assert oracle.compact_i32(x, 2**31 - 1).size == 0                 # nothing exceeds INT_MAX
+    allbut = oracle.compact_i32(x, -(2**31))                           # everything but INT_MIN
+    assert np.array_equal(allbut, x[x != -(2**31)])
+    for t in (-(2**30), 0, 12345):
+        y = oracle.compact_i32(x, t)
+        assert y.size == int(np.count_nonzero(x > t))
+        assert np.all(y > t)
+        # the kept elements appear in input order: their positions in x increase
+        pos = np.nonzero(x > t)[0]
+        assert np.array_equal(x[pos], y)
