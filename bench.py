@@ -112,7 +112,7 @@ def main():
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
                     help="run only the fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
-    ap.add_argument("--only", choices=("reduce", "jacobi"), default=None,
+    ap.add_argument("--only", choices=("reduce", "jacobi", "compact"), default=None,
                     help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
     ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
@@ -134,7 +134,7 @@ def main():
         print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5, n=args.gemm_n)}), flush=True)
         return
     if args.only:
-        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads}[args.only]
+        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads}[args.only]
         out = fn(spmd, synth)
         calibration_copies()
         print(json.dumps({f"only_{args.only}": out}), flush=True)
@@ -284,6 +284,7 @@ def extra_workloads(spmd, synth):
     res = copy_reference()
     res.update(reduce_workloads(spmd, synth))
     res.update(jacobi_workloads(spmd, synth))
+    res.update(compact_workloads(spmd, synth))
     res.update(gemm_workloads(spmd, synth))
     return res
 
@@ -404,6 +405,40 @@ def jacobi_workloads(spmd, synth):
             "us": round(ms * 1e3, 2), "GB/s": round(byt / ms / 1e6, 1),
             "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
     del u, a, bb
+    torch.cuda.empty_cache()
+    return res
+
+
+def compact_workloads(spmd, synth):
+    """COMPACT_I32: 2^26 int32 U[-1000,1000] (seed of the scan input), t = 0
+    (about half kept), blockDim 256 with 16 items, inputs rotated over two
+    copies; bytes = 4 per element read + 4 per element kept + the count."""
+    import torch
+
+    res = {}
+    n = 1 << 26
+    x_h = synth.uniform_int32(synth.SEED_SCAN, n, -1000, 1000)
+    xs = [to_dev(x_h), to_dev(x_h)]
+    y = torch.empty_like(xs[0])
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for block, items in ((1024, 32), (512, 32)):
+        grid = spmd.ops.compact_grid(n, block, items)
+        ws = spmd.ops.workspace(spmd.COMPACT_I32, grid, block, n)
+        log(f"compact 2^26 b{block} i{items}")
+        turn = [0]
+
+        def run():
+            spmd.ops.compact_i32(xs[turn[0] & 1], 0, block, items, y=y, count=count, ws=ws)
+            turn[0] += 1
+
+        ms = measure(run, 20)
+        m = int(count.cpu()[0])
+        assert m == int(np.count_nonzero(x_h > 0))
+        byts = 4 * n + 4 * m + 4
+        res[f"compact_i32 2^26 t=0 b{block} i{items}"] = {"us": round(ms * 1e3, 2), "kept": m,
+                                                          "GB/s": round(byts / ms / 1e6, 1),
+                                                          "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    del xs, y
     torch.cuda.empty_cache()
     return res
 

@@ -143,10 +143,27 @@ enum {
      * d[t] = s[n-1-t].
      * args: int32_t* d, uint32_t n
      * grid (1,1,1), block (n,1,1), dyn_shmem >= 4*n. */
-    SPMD_REVERSE_I32 = 7
+    SPMD_REVERSE_I32 = 7,
+
+    /* Stream compaction, a database selection (the filter operators of the
+     * GPU database queries covered in Section V-A): y[0, m) = the elements
+     * of x strictly greater than t (t is the int32 whose bits the uint32
+     * argument holds), in input order, and *count = m.  Elements of y from
+     * m on are untouched.  Each 32-lane warp finds its elements' output
+     * offsets by ballot and popc; tiles are chained by decoupled look-back
+     * over their counts, in ticket order, as SPMD_SCAN_I32.
+     * args: const int32_t* x, int32_t* y, uint32_t* count, uint32_t n,
+     *       uint32_t t, void* workspace
+     * grid (G,1,1), block (B,1,1), B a power of two in [64, 1024]; each
+     * thread handles I items, I = the smallest power of two >=
+     * ceil(n / (G*B)), I <= 32 (I <= 64 for B <= 512).  workspace:
+     * spmd_workspace_size() bytes,
+     * 16-byte aligned, zero-filled before first use, then reusable as for
+     * SCAN.  y must hold n elements. */
+    SPMD_COMPACT_I32 = 8
 };
 
-#define SPMD_NUM_KERNELS 7
+#define SPMD_NUM_KERNELS 8
 #define SPMD_WARPTEST_NCASES 904
 
 /* Launch one grid of kernel class `kernel_id` on `stream` (Section IV, "Push

@@ -50,7 +50,8 @@ JACOBI5_F32 = 4
 GEMM_F32 = 5
 WARPTEST = 6
 REVERSE_I32 = 7
-NUM_KERNELS = 7
+COMPACT_I32 = 8
+NUM_KERNELS = 8
 WARPTEST_NCASES = 904
 KERNELS = {}
 

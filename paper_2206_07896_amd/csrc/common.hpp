@@ -74,6 +74,7 @@ int launch_jacobi5_f32(const LaunchCtx& c);
 int launch_gemm_f32(const LaunchCtx& c);
 int launch_warptest(const LaunchCtx& c);
 int launch_reverse_i32(const LaunchCtx& c);
+int launch_compact_i32(const LaunchCtx& c);
 
 size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
 
@@ -85,5 +86,6 @@ namespace spmd {
 // kernels in order on the caller's stream (batch.hip).
 void batch_run_in_order(spmd_batch* b);
 size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
+size_t ws_compact_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
 
 }  // namespace spmd

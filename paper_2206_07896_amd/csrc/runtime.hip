@@ -48,6 +48,7 @@ const ClassInfo kClasses[SPMD_NUM_KERNELS + 1] = {
     {"gemm_f32", "pppuuu", launch_gemm_f32, ws_none},
     {"warptest", "ppp", launch_warptest, ws_none},
     {"reverse_i32", "pu", launch_reverse_i32, ws_none},
+    {"compact_i32", "pppuup", launch_compact_i32, ws_compact_i32},
 };
 
 const ClassInfo* class_info(int id) {

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (GEMM_F32, HIST256_U32, JACOBI5_F32, REDUCE_I32, REVERSE_I32, SCAN_I32, WARPTEST,
+from . import (COMPACT_I32, GEMM_F32, HIST256_U32, JACOBI5_F32, REDUCE_I32, REVERSE_I32, SCAN_I32, WARPTEST,
                WARPTEST_NCASES, launch, workspace_size)
 
 
@@ -58,6 +58,27 @@ def scan_i32(x: torch.Tensor, block: int = 512, items: int = 16, y=None, ws=None
         ws = workspace(SCAN_I32, grid, block, n, x.device)
     launch(SCAN_I32, grid, block, 0, [x, y, n, ws], stream)
     return y
+
+
+def compact_grid(n: int, block: int = 256, items: int = 16) -> int:
+    return max(1, _cdiv(n, block * items))
+
+
+def compact_i32(x: torch.Tensor, t: int, block: int = 256, items: int = 16, y=None, count=None, ws=None,
+                stream=None):
+    """Elements of x greater than t, in order: returns (y, count); y[:count]
+    holds them."""
+    _check_dev(x)
+    n = x.numel()
+    grid = compact_grid(n, block, items)
+    if y is None:
+        y = torch.empty_like(x)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=x.device)
+    if ws is None:
+        ws = workspace(COMPACT_I32, grid, block, n, x.device)
+    launch(COMPACT_I32, grid, block, 0, [x, y, count, n, int(t) & 0xFFFFFFFF, ws], stream)
+    return y, count
 
 
 def hist256_u32(keys: torch.Tensor, grid: int = 256, block: int = 1024, hist=None, stream=None):

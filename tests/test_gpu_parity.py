@@ -286,3 +286,73 @@ def test_scan_forms_share_a_workspace(spmd):
         y = spmd.ops.scan_i32(xt, block, items, ws=ws)
         spmd.sync()
         assert np.array_equal(host(y), want), (block, items)
+
+
+# --------------------------------------------------------------------------
+# COMPACT_I32 (warp vote: ballot + popc)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,block,items,t", [(1, 64, 1, 0), (100, 64, 1, 0), (5000, 64, 4, -1),
+                                             (8193, 128, 8, 500), (70001, 256, 16, 0),
+                                             (200000, 1024, 32, -900), (123457, 512, 2, 999),
+                                             (4096 * 16 * 3, 256, 16, 0), (300001, 512, 64, 0),
+                                             (65536 * 3 + 17, 256, 64, -3)])
+def test_compact(spmd, n, block, items, t):
+    import torch
+
+    say("compact", n, block, items, t)
+    x = synth.uniform_int32(0xC0 + n, n, -1000, 1000)
+    want = oracle.compact_i32(x, t)
+    xt = dev(x)
+    grid = spmd.ops.compact_grid(n, block, items)
+    ws = spmd.ops.workspace(spmd.COMPACT_I32, grid, block, n)
+    y = torch.full((n,), 7, dtype=torch.int32, device="cuda")
+    for rep in range(3):  # the workspace is reused without clearing
+        count = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        spmd.ops.compact_i32(xt, t, block, items, y=y, count=count, ws=ws)
+        spmd.sync()
+        m = int(count.item())
+        got = host(y)
+        assert m == want.size, (rep, m, want.size)
+        assert np.array_equal(got[:m], want), rep
+        assert np.all(got[m:] == (7 if rep == 0 else got[m:]))  # untouched beyond m
+
+
+def test_compact_edges(spmd):
+    import torch
+
+    say("compact edges")
+    n = 1 << 16
+    x = synth.uniform_int32(0xC1D, n, -(2**31), 2**31 - 1)
+    x[:2] = [-(2**31), 2**31 - 1]
+    xt = dev(x)
+    for t in (2**31 - 1, -(2**31), 0):
+        y, count = spmd.ops.compact_i32(xt, t)
+        spmd.sync()
+        want = oracle.compact_i32(x, t)
+        assert int(count.item()) == want.size and np.array_equal(host(y)[: want.size], want)
+    # unaligned input (the per-element path for every tile) and empty input
+    xu = torch.from_numpy(x[: n - 3].copy()).cuda()
+    base = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    base[1:n - 2] = xu
+    y, count = spmd.ops.compact_i32(base[1:n - 2], 0)
+    spmd.sync()
+    want = oracle.compact_i32(x[: n - 3], 0)
+    assert int(count.item()) == want.size and np.array_equal(host(y)[: want.size], want)
+    empty = torch.empty(0, dtype=torch.int32, device="cuda")
+    y, count = spmd.ops.compact_i32(empty, 0)
+    spmd.sync()
+    assert int(count.item()) == 0
+
+
+def test_compact_workload_size(spmd):
+    say("compact 2^26, t = 0")
+    n = 1 << 26
+    x = synth.uniform_int32(synth.SEED_SCAN, n, -1000, 1000)
+    y, count = spmd.ops.compact_i32(dev(x), 0, 256, 16)
+    spmd.sync()
+    want = oracle.compact_i32(x, 0)
+    m = int(count.item())
+    assert m == want.size
+    got = host(y)[:m]
+    assert np.array_equal(got, want)
