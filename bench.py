@@ -112,7 +112,7 @@ def main():
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
                     help="run only the fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
-    ap.add_argument("--only", choices=("reduce", "jacobi", "compact"), default=None,
+    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain"), default=None,
                     help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
     ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
@@ -134,7 +134,8 @@ def main():
         print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5, n=args.gemm_n)}), flush=True)
         return
     if args.only:
-        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads}[args.only]
+        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads,
+              "chain": chain_workloads}[args.only]
         out = fn(spmd, synth)
         calibration_copies()
         print(json.dumps({f"only_{args.only}": out}), flush=True)
@@ -285,6 +286,7 @@ def extra_workloads(spmd, synth):
     res.update(reduce_workloads(spmd, synth))
     res.update(jacobi_workloads(spmd, synth))
     res.update(compact_workloads(spmd, synth))
+    res.update(chain_workloads(spmd, synth))
     res.update(gemm_workloads(spmd, synth))
     return res
 
@@ -406,6 +408,65 @@ def jacobi_workloads(spmd, synth):
             "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
     del u, a, bb
     torch.cuda.empty_cache()
+    return res
+
+
+def chain_workloads(spmd, synth):
+    """100 dependent Jacobi sweeps (each reads the previous one's output):
+    one spmd_launch per sweep from the host, the same launches captured in a
+    graph, and one batch of 100 instances with dependencies
+    (spmd_batch_create_dep), replayed from a graph -- once with every sweep
+    as its own grid (bpf 0) and once through the persistent queue."""
+    import torch
+
+    res = {}
+    sweeps = 100
+    for nn in (1024, 8192):
+        u_h = synth.uniform_f32(synth.SEED_JACOBI, nn * nn).reshape(nn, nn)
+        u0 = to_dev(u_h)
+        bufs = [u0.clone(), torch.empty_like(u0)]
+
+        def launches():
+            for t in range(sweeps):
+                spmd.ops.jacobi5_f32(bufs[t % 2], bufs[(t + 1) % 2], (16, 16), 1)
+
+        log(f"jacobi chain {nn}^2 x {sweeps}")
+        ms_host = measure(launches, 3, warmup=1)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            launches()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            launches()
+        ms_graph = measure(g.replay, 3, warmup=1)
+        bufs[0].copy_(u0)
+        g.replay()
+        torch.cuda.synchronize()
+        ref = bufs[sweeps % 2].clone()
+        del g
+        items = [(spmd.JACOBI5_F32, nn, nn, 256, bufs[t % 2], bufs[(t + 1) % 2]) for t in range(sweeps)]
+        deps = [None] + list(range(sweeps - 1))
+        rec = {"ms_one_launch_per_sweep": round(ms_host, 3), "ms_launches_captured_graph": round(ms_graph, 3)}
+        same = True
+        for name, sched in (("own_grids", (256, 4, 0)), ("queue", (512, 4, 8))):
+            b = spmd.batch.Batch(items, [sched] * sweeps, deps=deps)
+            bufs[0].copy_(u0)
+            b.graph_launch()
+            spmd.sync()
+            same = same and bool(torch.equal(ref, bufs[sweeps % 2]))
+            ms = measure(b.graph_launch, 3, warmup=1)
+            spmd.sync()
+            b.close()
+            rec[f"ms_dependent_batch_{name}"] = round(ms, 3)
+            rec[f"schedule_{name}"] = list(sched)
+        rec["GB/s_dependent_batch_own_grids"] = round(8 * nn * nn * sweeps / rec["ms_dependent_batch_own_grids"] / 1e6, 1)
+        rec["outputs_identical"] = same
+        res[f"jacobi chain {nn}^2 x {sweeps} sweeps"] = rec
+        del bufs, u0
+        torch.cuda.empty_cache()
     return res
 
 

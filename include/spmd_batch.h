@@ -34,7 +34,11 @@ extern "C" {
  * cells per thread down a column, 1, 2, 4 or 8, with blocks of 64 x
  * block/64 threads); `bpf` logical blocks per fetch (>= 1; a SCAN
  * instance always fetches one tile at a time, since the tiles of one fetch
- * run in sequence and its successor waits on the last of them). */
+ * run in sequence and its successor waits on the last of them).  bpf 0
+ * takes the instance out of the queue: it runs as its class's own grid,
+ * one logical block per workgroup, dispatched by the hardware (the choice
+ * for one large instance alone in its level, e.g. a sweep of a dependent
+ * stencil chain). */
 typedef struct {
     uint32_t block;
     uint32_t items;
@@ -73,9 +77,30 @@ size_t spmd_batch_workspace_size(const spmd_batch_item* items, const spmd_schedu
 int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, int n, void* workspace,
                       size_t ws_bytes, uint32_t workers_per_cu, spmd_batch** out);
 
+/* Dependencies between instances (the device-side counterpart of the
+ * barrier inserted between an asynchronous kernel and work that reads its
+ * results, Section III-C1; the queue of Section IV itself keeps no order
+ * between kernels).  dep[i] is the index of an earlier instance
+ * (dep[i] < i) whose results instance i reads, or SPMD_NO_DEP; a NULL `dep`
+ * means none.  Instance i then sits one dependency level above dep[i]; each
+ * run executes the levels one after another, every level as one persistent
+ * kernel per (class, block size) queue present in it, so a chain such as
+ * 100 Jacobi sweeps is one batch, one graph, and no host round trip.  An
+ * instance may read from several earlier instances as long as they all sit
+ * below its level (levels are ordered as a whole).  dep[i] >= i (including
+ * a self-dependency) is SPMD_ERR_ARGS.  Without dependencies the result is
+ * the plain create's. */
+#define SPMD_NO_DEP 0xFFFFFFFFu
+
+size_t spmd_batch_workspace_size_dep(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep,
+                                     int n);
+
+int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep, int n,
+                          void* workspace, size_t ws_bytes, uint32_t workers_per_cu, spmd_batch** out);
+
 /* Run the batch on `stream`: a prologue kernel clears the per-run state,
- * then one persistent kernel per non-empty (class, block size) queue drains
- * it. */
+ * then, level by level, one persistent kernel per non-empty (class, block
+ * size) queue drains it. */
 int spmd_batch_launch(spmd_batch* b, void* stream);
 
 /* The same work as spmd_batch_launch, replayed from a hipGraph captured on

@@ -30,6 +30,12 @@ _lib.spmd_batch_workspace_size.restype = ctypes.c_size_t
 _lib.spmd_batch_create.argtypes = [ctypes.POINTER(BatchItem), ctypes.POINTER(Schedule), ctypes.c_int, _P,
                                    ctypes.c_size_t, _U32, ctypes.POINTER(_P)]
 _lib.spmd_batch_create.restype = ctypes.c_int
+_lib.spmd_batch_workspace_size_dep.argtypes = [ctypes.POINTER(BatchItem), ctypes.POINTER(Schedule), _P, ctypes.c_int]
+_lib.spmd_batch_workspace_size_dep.restype = ctypes.c_size_t
+_lib.spmd_batch_create_dep.argtypes = [ctypes.POINTER(BatchItem), ctypes.POINTER(Schedule), _P, ctypes.c_int, _P,
+                                       ctypes.c_size_t, _U32, ctypes.POINTER(_P)]
+_lib.spmd_batch_create_dep.restype = ctypes.c_int
+NO_DEP = 0xFFFFFFFF
 for _f in ("spmd_batch_launch", "spmd_batch_graph_launch", "spmd_batch_launch_each"):
     getattr(_lib, _f).argtypes = [_P, _P]
     getattr(_lib, _f).restype = ctypes.c_int
@@ -78,10 +84,17 @@ class Batch:
     one schedule (block, items, bpf) each.  Tensors must stay alive while
     the batch is used; the batch keeps references to them."""
 
-    def __init__(self, items, schedules, workers_per_cu: int = 0, device=None):
+    def __init__(self, items, schedules, workers_per_cu: int = 0, device=None, deps=None):
+        """deps: optional list, deps[i] = index of an earlier instance whose
+        output instance i reads, or None (spmd_batch_create_dep)."""
         n = len(items)
         if n == 0 or len(schedules) != n:
             raise SpmdError(-4, "Batch: need one schedule per item")
+        dep_arr = None
+        if deps is not None:
+            if len(deps) != n:
+                raise SpmdError(-4, "Batch: need one dependency entry per item")
+            dep_arr = (_U32 * n)(*[NO_DEP if d is None else int(d) for d in deps])
         self._keep = []
         arr = (BatchItem * n)()
         sch = (Schedule * n)()
@@ -90,16 +103,17 @@ class Batch:
             self._keep += [tin, tout]
         for i, (b, it, bpf) in enumerate(schedules):
             sch[i] = Schedule(int(b), int(it), int(bpf))
-        size = int(_lib.spmd_batch_workspace_size(arr, sch, n))
+        size = int(_lib.spmd_batch_workspace_size_dep(arr, sch, dep_arr, n))
         if size == 0:
-            raise SpmdError(-2, "spmd_batch_workspace_size (invalid items or schedules)")
+            raise SpmdError(-2, "spmd_batch_workspace_size (invalid items, schedules or dependencies)")
         raw = torch.empty(size + 256, dtype=torch.uint8, device=device or "cuda")
         off = (-raw.data_ptr()) % 256
         self.workspace = raw[off:off + size]
         self._raw = raw
         h = _P()
-        _check(_lib.spmd_batch_create(arr, sch, n, self.workspace.data_ptr(), size, workers_per_cu, ctypes.byref(h)),
-               "spmd_batch_create")
+        _check(_lib.spmd_batch_create_dep(arr, sch, dep_arr, n, self.workspace.data_ptr(), size, workers_per_cu,
+                                          ctypes.byref(h)), "spmd_batch_create")
+        self._deps = dep_arr
         self._h = h
         self.n = n
         self._items = arr

@@ -2,24 +2,30 @@
 //
 // Queue layout (all in the caller's workspace):
 //   run area    cleared by the prologue kernel on every run:
-//                 16 fetch cursors (one per (class, block size) group,
-//                 64 B apart),
+//                 one fetch cursor per segment, 64 B apart,
 //                 then per-instance scratch (REDUCE: ticket on its own
 //                 line + one status word per block; SCAN: one status
 //                 word per tile), 256-byte aligned
 //   each area   scratch of the one-launch-per-instance baseline (cleared
 //               once at creation; those launches re-arm it themselves)
 //   descriptors one 64-byte BatchDesc per instance (immutable)
-//   chunk maps  per group, the instance of every chunk, in queue order
+//   chunk maps  per segment, the instance of every chunk, in queue order
+//
+// A segment is the work of one persistent kernel: the instances of one
+// (class, block size) group at one dependency level.  An instance with no
+// dependency is at level 0, one that reads an earlier instance's output is
+// one level above it; the levels run one after another, the segments of a
+// level side by side.
 //
 // A chunk is up to `bpf` consecutive logical blocks of one instance; the
-// chunks of a group are numbered instance by instance, blocks ascending,
+// chunks of a segment are numbered instance by instance, blocks ascending,
 // so a scan's tiles are fetched in order (its look-back waits only for
 // tiles fetched earlier).  A persistent workgroup takes a chunk with one
-// relaxed atomic add on its group's cursor and requests the next chunk as
-// soon as it starts the current one, so the atomic's round trip overlaps
-// the block bodies.  It exits when the cursor passes the group's chunk
-// count, so every workgroup ends after finitely many fetches.
+// relaxed atomic add on its segment's cursor and requests the next chunk
+// as soon as it starts the current one, so the atomic's round trip
+// overlaps the block bodies.  It exits when the cursor passes the
+// segment's chunk count, so every workgroup ends after finitely many
+// fetches.
 #include <string.h>
 
 #include <algorithm>
@@ -54,7 +60,6 @@ static_assert(sizeof(BatchDesc) == 64, "descriptor is 64 bytes");
 // one class body, which keeps its register use -- and so the number of
 // resident workers -- at that class's own level.
 constexpr int NSIZES = 4, NCLS = 4, NGROUPS = NSIZES * NCLS;
-constexpr size_t RUN_HEADER = 64 * NGROUPS;  // one 64-byte cursor slot per group
 constexpr uint32_t SIZE_B[NSIZES] = {64, 128, 256, 512};
 constexpr int CLS_ID[NCLS] = {SPMD_REDUCE_I32, SPMD_SCAN_I32, SPMD_HIST256_U32, SPMD_JACOBI5_F32};
 
@@ -167,9 +172,22 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
     __shared__ BatchLdsOf<CLS, B> L;
     __shared__ uint32_t s_next;
     const uint32_t t = threadIdx.x;
-    if (t == 0) s_next = atomic_add_dev(cursor, 1u);
-    __syncthreads();
-    uint32_t c = __builtin_amdgcn_readfirstlane(s_next);
+    // Chunk numbers handed out by the cursor.  Every class but SCAN takes
+    // its first chunk statically (chunk blockIdx.x; the grid never exceeds
+    // the chunk count), which saves one serialized atomic per worker.  SCAN
+    // takes every chunk from the cursor, so a tile is only ever owned by a
+    // running worker and the tiles its look-back waits on are in progress
+    // even when other kernels hold some of the compute units.
+    constexpr bool STATIC_FIRST = CLS != SPMD_SCAN_I32;
+    const uint32_t base = STATIC_FIRST ? gridDim.x : 0u;
+    uint32_t c;
+    if constexpr (STATIC_FIRST) {
+        c = blockIdx.x;
+    } else {
+        if (t == 0) s_next = atomic_add_dev(cursor, 1u);
+        __syncthreads();
+        c = __builtin_amdgcn_readfirstlane(s_next);
+    }
     while (c < total_chunks) {
         __syncthreads();  // every thread has read s_next
         // The next fetch is issued early so its round trip overlaps this
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
         uint32_t nxt = 0;
         bool fetched = false;
         if (CLS != SPMD_SCAN_I32 && t == 0) {
-            nxt = atomic_add_dev(cursor, 1u);
+            nxt = base + atomic_add_dev(cursor, 1u);
             fetched = true;
         }
         const BatchDesc d = descs[chunk_inst[c]];
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
         } else {
             auto fetch_once = [&]() {
                 if (!fetched) {
-                    nxt = atomic_add_dev(cursor, 1u);
+                    nxt = base + atomic_add_dev(cursor, 1u);
                     fetched = true;
                 }
             };
@@ -204,7 +222,7 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
             }
         }
         if (t == 0) {
-            if (!fetched) nxt = atomic_add_dev(cursor, 1u);
+            if (!fetched) nxt = base + atomic_add_dev(cursor, 1u);
             s_next = nxt;
         }
         __syncthreads();
@@ -228,6 +246,29 @@ __global__ __launch_bounds__(256) void batch_prologue_kernel(u32x4* run, uint64_
 
 using namespace spmd;
 
+// The instances of one group at one dependency level: one persistent
+// kernel per run.
+struct BatchSegment {
+    uint32_t level;
+    int group;
+    size_t chunk_off;  // its chunk map in the workspace
+    uint32_t chunks;   // chunks in its queue
+    uint32_t grid;     // persistent workgroups
+    int direct;        // an instance with bpf 0, run as its own grid; -1 for a queue
+};
+
+struct SegKey {
+    uint32_t level;
+    int group;
+    int direct;
+    bool operator<(const SegKey& o) const {
+        if (level != o.level) return level < o.level;
+        if (group != o.group) return group < o.group;
+        return direct < o.direct;
+    }
+    bool operator==(const SegKey& o) const { return level == o.level && group == o.group && direct == o.direct; }
+};
+
 struct spmd_batch {
     int n = 0;
     std::vector<spmd_batch_item> items;
@@ -235,9 +276,7 @@ struct spmd_batch {
     std::vector<uint64_t> blocks;  // logical blocks per instance
     uint8_t* ws = nullptr;
     size_t run_bytes = 0, each_off = 0, desc_off = 0, hist_off = 0;
-    size_t chunk_off[NGROUPS] = {};
-    uint32_t chunks[NGROUPS] = {};
-    uint32_t grid[NGROUPS] = {};
+    std::vector<BatchSegment> seg;  // by level, then group
     std::vector<size_t> each_ws;        // per instance: offset of its standalone workspace
     std::vector<size_t> each_partials;  // per instance (REDUCE): offset of its partials
     uint32_t nhist = 0;
@@ -247,10 +286,10 @@ struct spmd_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // fork/join of the group kernels over side streams (two or more groups)
-    int ngroups_active = 0;
-    hipEvent_t ev_fork = nullptr;
-    hipEvent_t ev_join[NGROUPS] = {};
+    // fork/join of the segment kernels of one level over side streams
+    // (levels with two or more segments); per level / per segment, null
+    // where unused, all null when the segments run in order
+    std::vector<hipEvent_t> ev_fork, ev_join;
 };
 
 namespace {
@@ -277,14 +316,17 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // first tile of the next chunk needs this chunk's last tile's aggregate,
 // so chunks of several tiles would run the instance serially.
 uint32_t effective_bpf(const spmd_batch_item& it, const spmd_schedule& s) {
-    return it.kernel_id == SPMD_SCAN_I32 ? 1u : s.bpf;
+    return (it.kernel_id == SPMD_SCAN_I32 || s.bpf == 0) ? 1u : s.bpf;
 }
+
+// bpf 0: the instance runs as its class's own grid, outside the queue.
+bool is_direct(const spmd_schedule& s) { return s.bpf == 0; }
 
 uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // Logical blocks of an item under a schedule, 0 if the pair is invalid.
 uint64_t item_blocks(const spmd_batch_item& it, const spmd_schedule& s) {
-    if (group_of(it.kernel_id, s.block) < 0 || s.bpf == 0) return 0;
+    if (group_of(it.kernel_id, s.block) < 0) return 0;
     const uint64_t per = (uint64_t)s.block * s.items;
     switch (it.kernel_id) {
     case SPMD_REDUCE_I32:
@@ -326,18 +368,35 @@ size_t each_scratch(const spmd_batch_item& it, uint64_t nb) {
 }
 
 struct Layout {
-    size_t run_bytes, each_off, each_bytes, desc_off, hist_off, chunk_off[NGROUPS], total;
-    uint32_t chunks[NGROUPS];
+    size_t cursor_bytes, run_bytes, each_off, each_bytes, desc_off, hist_off, total;
     uint32_t nhist;
+    std::vector<uint32_t> level;     // per instance
+    std::vector<BatchSegment> seg;   // by level, then group
+    std::vector<uint32_t> seg_of;    // per instance: its segment
 };
 
-int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, int n, std::vector<uint64_t>& blocks,
-                Layout& L) {
+// Dependency levels: dep[i] is an earlier instance (dep[i] < i) or NO_DEP;
+// an instance sits one level above the one it reads.
+int dep_levels(const uint32_t* dep, int n, std::vector<uint32_t>& level) {
+    level.assign(n, 0);
+    if (!dep) return SPMD_OK;
+    for (int i = 0; i < n; ++i) {
+        if (dep[i] == SPMD_NO_DEP) continue;
+        if (dep[i] >= (uint32_t)i) return SPMD_ERR_ARGS;
+        level[i] = level[dep[i]] + 1;
+    }
+    return SPMD_OK;
+}
+
+int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep, int n,
+                std::vector<uint64_t>& blocks, Layout& L) {
     if (n <= 0 || !items || !sched) return SPMD_ERR_ARGS;
     blocks.assign(n, 0);
-    size_t run = RUN_HEADER, each = 0;
-    uint64_t ch[NGROUPS] = {};
+    int rc = dep_levels(dep, n, L.level);
+    if (rc) return rc;
+    size_t run = 0, each = 0;
     uint32_t nhist = 0;
+    std::vector<SegKey> key(n);
     for (int i = 0; i < n; ++i) {
         const auto& it = items[i];
         const auto& s = sched[i];
@@ -352,21 +411,37 @@ int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, int n,
         blocks[i] = nb;
         run += run_scratch(it, nb);
         each += each_scratch(it, nb);
-        ch[group_of(it.kernel_id, s.block)] += cdiv(nb, effective_bpf(it, s));
+        key[i] = SegKey{L.level[i], group_of(it.kernel_id, s.block), is_direct(s) ? i : -1};
         if (it.kernel_id == SPMD_HIST256_U32) ++nhist;
     }
-    for (int g = 0; g < NGROUPS; ++g)
-        if (ch[g] >= (1ull << 32) - 1) return SPMD_ERR_INVALID_DIM;
-    L.run_bytes = align_up(run, 256);
+    // segments in (level, group, queue first) order
+    std::vector<SegKey> keys(key);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    L.seg.assign(keys.size(), BatchSegment{});
+    std::vector<uint64_t> ch(keys.size(), 0);
+    L.seg_of.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        const uint32_t k = (uint32_t)(std::lower_bound(keys.begin(), keys.end(), key[i]) - keys.begin());
+        L.seg_of[i] = k;
+        if (key[i].direct < 0) ch[k] += cdiv(blocks[i], effective_bpf(items[i], sched[i]));
+    }
+    L.cursor_bytes = align_up(64 * keys.size(), 256);
+    L.run_bytes = align_up(L.cursor_bytes + run, 256);
     L.each_off = L.run_bytes;
     L.each_bytes = align_up(each, 256);
     L.desc_off = L.each_off + L.each_bytes;
     L.hist_off = align_up(L.desc_off + sizeof(BatchDesc) * (size_t)n, 256);
     size_t off = align_up(L.hist_off + 8 * (size_t)nhist, 256);
-    for (int g = 0; g < NGROUPS; ++g) {
-        L.chunk_off[g] = off;
-        L.chunks[g] = (uint32_t)ch[g];
-        off = align_up(off + 4 * ch[g], 256);
+    for (size_t k = 0; k < keys.size(); ++k) {
+        if (ch[k] >= (1ull << 31)) return SPMD_ERR_INVALID_DIM;  // chunk numbers + grid fit 32 bits
+        BatchSegment& g = L.seg[k];
+        g.level = keys[k].level;
+        g.group = keys[k].group;
+        g.direct = keys[k].direct;
+        g.chunk_off = off;
+        g.chunks = (uint32_t)ch[k];
+        off = align_up(off + 4 * ch[k], 256);
     }
     L.total = off;
     L.nhist = nhist;
@@ -439,6 +514,60 @@ int side_streams(const DevInfo* di, hipStream_t** out) {
     return SPMD_OK;
 }
 
+// Instance i as its class's own grid (spmd_launch: one logical block per
+// workgroup, the hardware dispatcher as the queue), with its scratch in the
+// each area.
+int launch_direct(spmd_batch* b, int i, hipStream_t stream) {
+    const auto& it = b->items[i];
+    const auto& s = b->sched[i];
+    const uint32_t nb = (uint32_t)b->blocks[i];
+    const void* in = it.in;
+    void* outp = it.out;
+    uint32_t n = it.n, ny = it.ny;
+    void* ws = b->ws + b->each_ws[i];
+    void* partials = b->ws + b->each_partials[i];
+    switch (it.kernel_id) {
+    case SPMD_REDUCE_I32: {
+        void* args[] = {&in, &partials, &outp, &n, &ws};
+        return spmd_launch(SPMD_REDUCE_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+    }
+    case SPMD_SCAN_I32: {
+        if (n == 0) return SPMD_OK;
+        void* args[] = {&in, &outp, &n, &ws};
+        return spmd_launch(SPMD_SCAN_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+    }
+    case SPMD_HIST256_U32: {
+        void* args[] = {&in, &outp, &n};
+        return spmd_launch(SPMD_HIST256_U32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
+    }
+    case SPMD_JACOBI5_F32: {
+        void* args[] = {&in, &outp, &n, &ny};
+        const uint32_t gx = (uint32_t)cdiv(n, 64);
+        return spmd_launch(SPMD_JACOBI5_F32, {gx, nb / gx, 1}, {64, s.block / 64, 1}, 0, args, stream);
+    }
+    }
+    return SPMD_ERR_INVALID_KERNEL;
+}
+
+int launch_segment(const spmd_batch* b, const BatchSegment& g, hipStream_t gs, const BatchDesc* descs,
+                   uint32_t* cursor, uint32_t* err) {
+    const uint32_t* cmap = reinterpret_cast<const uint32_t*>(b->ws + g.chunk_off);
+    const uint32_t block = SIZE_B[g.group % NSIZES];
+    const dim3 gr(g.grid);
+    switch (CLS_ID[g.group / NSIZES]) {
+    case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
+    case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
+    case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
+    case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
+}
+
+// Prologue, then the levels in order on `s`; within a level the segments
+// fork onto side streams and join back before the next level starts, so a
+// level reads what every earlier level wrote (the kernel boundaries make
+// those writes visible to all XCDs).
 int enqueue_run(spmd_batch* b, hipStream_t s) {
     clear_stale_error();
     const uint64_t run_words = b->run_bytes / 16;
@@ -450,54 +579,53 @@ int enqueue_run(spmd_batch* b, hipStream_t s) {
     uint32_t* err = b->dev->err_word;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e);
-    const bool fork = b->ngroups_active >= 2 && b->ev_fork != nullptr;
     hipStream_t* side = nullptr;
-    if (fork) {
-        int rc = side_streams(b->dev, &side);
-        if (rc) return rc;
-        if ((e = hipEventRecord(b->ev_fork, s)) != hipSuccess) return hip_fail(e);
-    }
-    int k = 0;
-    for (int g = 0; g < NGROUPS; ++g) {
-        if (!b->chunks[g]) continue;
-        hipStream_t gs = s;
+    const size_t nseg = b->seg.size();
+    for (size_t lo = 0; lo < nseg;) {
+        size_t hi = lo;
+        while (hi < nseg && b->seg[hi].level == b->seg[lo].level) ++hi;
+        const uint32_t lev = b->seg[lo].level;
+        const bool fork = hi - lo >= 2 && lev < b->ev_fork.size() && b->ev_fork[lev] != nullptr;
         if (fork) {
-            gs = side[k];
-            if ((e = hipStreamWaitEvent(gs, b->ev_fork, 0)) != hipSuccess) return hip_fail(e);
+            int rc = side ? SPMD_OK : side_streams(b->dev, &side);
+            if (rc) return rc;
+            if ((e = hipEventRecord(b->ev_fork[lev], s)) != hipSuccess) return hip_fail(e);
         }
-        const uint32_t* cmap = reinterpret_cast<const uint32_t*>(b->ws + b->chunk_off[g]);
-        uint32_t* cursor = reinterpret_cast<uint32_t*>(b->ws + 64 * g);
-        const uint32_t block = SIZE_B[g % NSIZES];
-        const dim3 gr(b->grid[g]);
-        switch (CLS_ID[g / NSIZES]) {
-        case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
-        case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, b->chunks[g], cursor, err); break;
+        for (size_t k = lo; k < hi; ++k) {
+            hipStream_t gs = s;
+            if (fork) {
+                gs = side[k - lo];
+                if ((e = hipStreamWaitEvent(gs, b->ev_fork[lev], 0)) != hipSuccess) return hip_fail(e);
+            }
+            const BatchSegment& g = b->seg[k];
+            int rc = g.direct >= 0 ? launch_direct(b, g.direct, gs)
+                                   : launch_segment(b, g, gs, descs, reinterpret_cast<uint32_t*>(b->ws + 64 * k), err);
+            if (rc) return rc;
+            if (fork) {
+                if ((e = hipEventRecord(b->ev_join[k], gs)) != hipSuccess) return hip_fail(e);
+                if ((e = hipStreamWaitEvent(s, b->ev_join[k], 0)) != hipSuccess) return hip_fail(e);
+            }
         }
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
-        if (fork) {
-            if ((e = hipEventRecord(b->ev_join[k], gs)) != hipSuccess) return hip_fail(e);
-            if ((e = hipStreamWaitEvent(s, b->ev_join[k], 0)) != hipSuccess) return hip_fail(e);
-        }
-        ++k;
+        lo = hi;
     }
     return SPMD_OK;
+}
+
+void destroy_events(spmd_batch* b) {
+    for (hipEvent_t ev : b->ev_fork)
+        if (ev) hipEventDestroy(ev);
+    for (hipEvent_t ev : b->ev_join)
+        if (ev) hipEventDestroy(ev);
+    b->ev_fork.clear();
+    b->ev_join.clear();
 }
 
 }  // namespace
 
 // For plans destroyed right after one enqueue (spmd_launch_batch): run the
-// group kernels in order on the caller's stream, so no event outlives its
+// segment kernels in order on the caller's stream, so no event outlives its
 // plan while the GPU still has to reach it.
-void spmd::batch_run_in_order(spmd_batch* b) {
-    if (b->ev_fork) hipEventDestroy(b->ev_fork);
-    for (int g = 0; g < NGROUPS; ++g)
-        if (b->ev_join[g]) hipEventDestroy(b->ev_join[g]);
-    b->ev_fork = nullptr;
-    for (int g = 0; g < NGROUPS; ++g) b->ev_join[g] = nullptr;
-    b->ngroups_active = 1;
-}
+void spmd::batch_run_in_order(spmd_batch* b) { destroy_events(b); }
 
 extern "C" {
 
@@ -506,20 +634,30 @@ uint64_t spmd_batch_item_blocks(const spmd_batch_item* item, const spmd_schedule
     return item_blocks(*item, *sched);
 }
 
-size_t spmd_batch_workspace_size(const spmd_batch_item* items, const spmd_schedule* sched, int n) {
+size_t spmd_batch_workspace_size_dep(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep,
+                                     int n) {
     std::vector<uint64_t> blocks;
     Layout L;
-    if (plan_layout(items, sched, n, blocks, L) != SPMD_OK) return 0;
+    if (plan_layout(items, sched, dep, n, blocks, L) != SPMD_OK) return 0;
     return L.total;
+}
+
+size_t spmd_batch_workspace_size(const spmd_batch_item* items, const spmd_schedule* sched, int n) {
+    return spmd_batch_workspace_size_dep(items, sched, nullptr, n);
 }
 
 int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, int n, void* workspace,
                       size_t ws_bytes, uint32_t workers_per_cu, spmd_batch** out) {
+    return spmd_batch_create_dep(items, sched, nullptr, n, workspace, ws_bytes, workers_per_cu, out);
+}
+
+int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep, int n,
+                          void* workspace, size_t ws_bytes, uint32_t workers_per_cu, spmd_batch** out) {
     if (!out) return SPMD_ERR_ARGS;
     *out = nullptr;
     std::vector<uint64_t> blocks;
     Layout L;
-    int rc = plan_layout(items, sched, n, blocks, L);
+    int rc = plan_layout(items, sched, dep, n, blocks, L);
     if (rc) return rc;
     if (!workspace || ((uintptr_t)workspace % 256) || ws_bytes < L.total) return SPMD_ERR_WORKSPACE;
     const DevInfo* di = nullptr;
@@ -537,23 +675,21 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
     b->hist_off = L.hist_off;
     b->nhist = L.nhist;
     b->dev = di;
-    for (int g = 0; g < NGROUPS; ++g) {
-        b->chunk_off[g] = L.chunk_off[g];
-        b->chunks[g] = L.chunks[g];
-    }
+    b->seg = L.seg;
 
     // descriptors, chunk maps, histogram list, baseline scratch offsets
+    const size_t nseg = b->seg.size();
     std::vector<BatchDesc> descs(n);
-    std::vector<std::vector<uint32_t>> cmap(NGROUPS);
-    for (int g = 0; g < NGROUPS; ++g) cmap[g].reserve(L.chunks[g]);
+    std::vector<std::vector<uint32_t>> cmap(nseg);
+    for (size_t k = 0; k < nseg; ++k) cmap[k].reserve(b->seg[k].chunks);
     std::vector<uint64_t> hist_ptrs;
-    size_t run = RUN_HEADER, each = L.each_off;
+    size_t run = L.cursor_bytes, each = L.each_off;
     b->each_ws.assign(n, 0);
     b->each_partials.assign(n, 0);
     for (int i = 0; i < n; ++i) {
         const auto& it = items[i];
         const auto& s = sched[i];
-        const int g = group_of(it.kernel_id, s.block);
+        std::vector<uint32_t>& cm = cmap[L.seg_of[i]];
         BatchDesc& d = descs[i];
         memset(&d, 0, sizeof d);
         d.cls = (uint32_t)it.kernel_id;
@@ -562,7 +698,7 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
         d.nblocks = (uint32_t)blocks[i];
         d.items = s.items;
         d.bpf = effective_bpf(it, s);
-        d.chunk0 = (uint32_t)cmap[g].size();
+        d.chunk0 = (uint32_t)cm.size();
         d.in = (uint64_t)(uintptr_t)it.in;
         d.out = (uint64_t)(uintptr_t)it.out;
         d.ws = (uint64_t)(uintptr_t)(b->ws + run);
@@ -575,8 +711,8 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
         case SPMD_JACOBI5_F32: d.aux = (uint32_t)cdiv(it.n, 64); break;
         }
         if (it.kernel_id == SPMD_HIST256_U32) hist_ptrs.push_back((uint64_t)(uintptr_t)it.out);
-        const uint64_t nch = cdiv(blocks[i], d.bpf);
-        for (uint64_t k = 0; k < nch; ++k) cmap[g].push_back((uint32_t)i);
+        const uint64_t nch = is_direct(s) ? 0 : cdiv(blocks[i], d.bpf);
+        for (uint64_t k = 0; k < nch; ++k) cm.push_back((uint32_t)i);
         run += run_scratch(it, blocks[i]);
         if (it.kernel_id == SPMD_REDUCE_I32) {
             b->each_ws[i] = each;
@@ -591,33 +727,42 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
     hipError_t e = hipMemcpy(b->ws + L.desc_off, descs.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && !hist_ptrs.empty())
         e = hipMemcpy(b->ws + L.hist_off, hist_ptrs.data(), 8 * hist_ptrs.size(), hipMemcpyHostToDevice);
-    for (int g = 0; g < NGROUPS && e == hipSuccess; ++g)
-        if (!cmap[g].empty())
-            e = hipMemcpy(b->ws + L.chunk_off[g], cmap[g].data(), 4 * cmap[g].size(), hipMemcpyHostToDevice);
+    for (size_t k = 0; k < nseg && e == hipSuccess; ++k)
+        if (!cmap[k].empty())
+            e = hipMemcpy(b->ws + b->seg[k].chunk_off, cmap[k].data(), 4 * cmap[k].size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && L.each_bytes) e = hipMemset(b->ws + L.each_off, 0, L.each_bytes);
     if (e != hipSuccess) {
         delete b;
         return hip_fail(e);
     }
-    for (int g = 0; g < NGROUPS; ++g) {
-        b->total_chunks += b->chunks[g];
-        if (!b->chunks[g]) continue;
+    for (BatchSegment& g : b->seg) {
+        b->total_chunks += g.chunks;
+        if (g.direct >= 0) continue;
         uint32_t pool = 0;
-        if ((rc = pool_size(CLS_ID[g / NSIZES], SIZE_B[g % NSIZES], workers_per_cu, di, &pool))) {
+        if ((rc = pool_size(CLS_ID[g.group / NSIZES], SIZE_B[g.group % NSIZES], workers_per_cu, di, &pool))) {
             delete b;
             return rc;
         }
-        b->grid[g] = (uint32_t)std::min<uint64_t>(pool, b->chunks[g]);
-        ++b->ngroups_active;
+        g.grid = (uint32_t)std::min<uint64_t>(pool, g.chunks);
     }
-    if (b->ngroups_active >= 2) {
-        e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-        for (int k = 0; k < b->ngroups_active && e == hipSuccess; ++k)
-            e = hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            spmd_batch_destroy(b);
-            return hip_fail(e);
+    // events for the levels that fork over two or more segments
+    const uint32_t nlevels = b->seg.back().level + 1;
+    b->ev_fork.assign(nlevels, nullptr);
+    b->ev_join.assign(nseg, nullptr);
+    e = hipSuccess;
+    for (size_t lo = 0; lo < nseg && e == hipSuccess;) {
+        size_t hi = lo;
+        while (hi < nseg && b->seg[hi].level == b->seg[lo].level) ++hi;
+        if (hi - lo >= 2) {
+            e = hipEventCreateWithFlags(&b->ev_fork[b->seg[lo].level], hipEventDisableTiming);
+            for (size_t k = lo; k < hi && e == hipSuccess; ++k)
+                e = hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming);
         }
+        lo = hi;
+    }
+    if (e != hipSuccess) {
+        spmd_batch_destroy(b);
+        return hip_fail(e);
     }
     *out = b;
     return SPMD_OK;
@@ -649,39 +794,7 @@ int spmd_batch_graph_launch(spmd_batch* b, void* stream) {
 int spmd_batch_launch_each(spmd_batch* b, void* stream) {
     if (!b) return SPMD_ERR_ARGS;
     for (int i = 0; i < b->n; ++i) {
-        const auto& it = b->items[i];
-        const auto& s = b->sched[i];
-        const uint32_t nb = (uint32_t)b->blocks[i];
-        const void* in = it.in;
-        void* outp = it.out;
-        uint32_t n = it.n, ny = it.ny;
-        void* ws = b->ws + b->each_ws[i];
-        void* partials = b->ws + b->each_partials[i];
-        int rc = SPMD_OK;
-        switch (it.kernel_id) {
-        case SPMD_REDUCE_I32: {
-            void* args[] = {&in, &partials, &outp, &n, &ws};
-            rc = spmd_launch(SPMD_REDUCE_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
-            break;
-        }
-        case SPMD_SCAN_I32: {
-            if (n == 0) break;
-            void* args[] = {&in, &outp, &n, &ws};
-            rc = spmd_launch(SPMD_SCAN_I32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
-            break;
-        }
-        case SPMD_HIST256_U32: {
-            void* args[] = {&in, &outp, &n};
-            rc = spmd_launch(SPMD_HIST256_U32, {nb, 1, 1}, {s.block, 1, 1}, 0, args, stream);
-            break;
-        }
-        case SPMD_JACOBI5_F32: {
-            void* args[] = {&in, &outp, &n, &ny};
-            const uint32_t gx = (uint32_t)cdiv(n, 64);
-            rc = spmd_launch(SPMD_JACOBI5_F32, {gx, nb / gx, 1}, {64, s.block / 64, 1}, 0, args, stream);
-            break;
-        }
-        }
+        const int rc = launch_direct(b, i, static_cast<hipStream_t>(stream));
         if (rc) return rc;
     }
     return SPMD_OK;
@@ -693,9 +806,7 @@ int spmd_batch_stats(const spmd_batch* b, uint64_t* blocks, uint64_t* chunks, ui
     if (blocks) *blocks = b->total_blocks;
     if (chunks) *chunks = b->total_chunks;
     if (persistent_launches) {
-        uint32_t k = 1;
-        for (int g = 0; g < NGROUPS; ++g) k += b->chunks[g] ? 1u : 0u;  // prologue + one per group
-        *persistent_launches = k;
+        *persistent_launches = 1u + (uint32_t)b->seg.size();  // prologue + one per segment
     }
     if (each_launches) *each_launches = b->each_launches;
     return SPMD_OK;
@@ -716,9 +827,7 @@ int spmd_batch_destroy(spmd_batch* b) {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
     if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-    if (b->ev_fork) hipEventDestroy(b->ev_fork);
-    for (int g = 0; g < NGROUPS; ++g)
-        if (b->ev_join[g]) hipEventDestroy(b->ev_join[g]);
+    destroy_events(b);
     delete b;
     return SPMD_OK;
 }

@@ -116,7 +116,7 @@ def test_batch_item_blocks(spmd):
     for bad in [(S, 100, 1, 96, 4), (S, 100, 1, 1024, 4), (R, 100, 1, 64, 3), (J, 100, 1, 64, 16), (J, 0, 5, 64, 1),
                 (6, 100, 1, 64, 1)]:
         assert ib(*bad) == 0, bad
-    assert ib(R, 100, 1, 64, 1, bpf=0) == 0
+    assert ib(R, 100, 1, 64, 1, bpf=0) == 2   # bpf 0 (own grid): same logical blocks
 
 
 def _items(spmd, specs):
@@ -267,3 +267,32 @@ def test_launch_batch_workspace_covers_every_schedule(spmd):
         sch = (B.Schedule * len(items))(*[B.Schedule(*c) for c in pick])
         need = lib.spmd_batch_workspace_size(iarr, sch, len(items))
         assert 0 < need <= bound
+
+
+def test_batch_dependencies_validated_on_host(spmd):
+    """dep[i] must name an earlier instance, in any queue; anything else is
+    refused before any device work."""
+    import ctypes as C
+
+    from paper_2206_07896_amd import batch as B
+
+    p = [0x10000, 0x20000, 0x30000]
+    items = (B.BatchItem * 3)(B.BatchItem(spmd.SCAN_I32, 1000, 1, 256, p[0], p[1]),
+                              B.BatchItem(spmd.HIST256_U32, 1000, 1, 256, p[1], p[2]),
+                              B.BatchItem(spmd.SCAN_I32, 1000, 1, 256, p[1], p[0]))
+    sch = (B.Schedule * 3)(*[B.Schedule(256, 4, 1)] * 3)
+    lib = spmd.lib()
+
+    def size(deps):
+        d = (C.c_uint32 * 3)(*[B.NO_DEP if v is None else v for v in deps])
+        return lib.spmd_batch_workspace_size_dep(items, sch, d, 3)
+
+    base = lib.spmd_batch_workspace_size(items, sch, 3)
+    assert base > 0
+    assert size([None, None, None]) == base           # no dependency: the plain plan
+    assert size([None, 0, None]) > 0                   # SCAN -> HIST
+    assert size([None, None, 0]) > 0                   # same queue, next level
+    assert size([None, None, 1]) > 0                   # HIST -> SCAN
+    assert size([None, 0, 1]) > 0                      # three levels
+    assert size([0, None, None]) == 0                  # itself
+    assert size([None, 2, None]) == 0                  # a later instance

@@ -42,6 +42,10 @@ def dev(a):
     return torch.from_numpy(a.view(np.int32) if a.dtype == np.uint32 else a).cuda()
 
 
+def host(t):
+    return t.cpu().numpy()
+
+
 def make_instances(spmd, count, seed, nmax_log2=16, include_edges=True):
     """Mixed instances with host inputs, device buffers and random schedules."""
     import torch
@@ -229,4 +233,92 @@ def test_mixed_workload_small(spmd):
             assert np.array_equal(got.view(np.uint32), oracle.hist256_u32(x, 1, 64)), i
         else:
             assert np.array_equal(got, oracle.jacobi5_f32(x, 16, 16)), i
+    b.close()
+
+
+@pytest.mark.parametrize("seed", [5])
+def test_batch_random_levels(spmd, seed):
+    """Seeded instances with random dependencies (no data flows along them):
+    many levels, several queues per level, every output still the
+    oracle's."""
+    rng = np.random.default_rng(seed)
+    insts = make_instances(spmd, 48, seed, nmax_log2=14)
+    deps = [None if i == 0 or rng.random() < 0.4 else int(rng.integers(0, i)) for i in range(len(insts))]
+    for it in insts:  # about one in five runs as its own grid (bpf 0)
+        if rng.random() < 0.2:
+            it["sched"] = (it["sched"][0], it["sched"][1], 0)
+    say("random levels", seed, deps, [it["sched"] for it in insts])
+    b = spmd.batch.Batch(items_of(insts), [it["sched"] for it in insts], deps=deps)
+    for mode in ("eager", "graph", "graph"):
+        scribble(insts)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        check_all(insts, f"random levels {mode}")
+    b.close()
+
+
+# --------------------------------------------------------------------------
+# Dependent instances (spmd_batch_create_dep)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sched", [(256, 4, 8), (64, 1, 3), (512, 8, 32), (256, 4, 0), (128, 2, 0)])
+def test_dependent_jacobi_chain_in_one_batch(spmd, sched):
+    """25 sweeps as 25 instances of one queue, each reading the previous
+    one's output: one batch, one launch per queue, bit-exact against 25
+    sweeps of the oracle, eagerly and over graph replays."""
+    import torch
+
+    ny, nx, sweeps = 131, 517, 25
+    say("dependent jacobi chain", ny, nx, sweeps, sched)
+    u = synth.uniform_f32(0xD5, ny * nx).reshape(ny, nx)
+    bufs = [dev(u), torch.empty((ny, nx), dtype=torch.float32, device="cuda")]
+    items = [(spmd.JACOBI5_F32, nx, ny, 256, bufs[t % 2], bufs[(t + 1) % 2]) for t in range(sweeps)]
+    deps = [None] + list(range(sweeps - 1))
+    b = spmd.batch.Batch(items, [sched] * sweeps, deps=deps)
+    want = oracle.jacobi5_f32_sweeps(u, sweeps)
+    for mode in ("eager", "graph", "graph"):
+        bufs[0].copy_(torch.from_numpy(u))
+        bufs[1].fill_(-1.0)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        assert np.array_equal(host(bufs[sweeps % 2]), want), mode
+    b.close()
+
+
+def test_dependency_across_queues(spmd):
+    """Three levels over queues in both orders: a Jacobi sweep, a scan of
+    its output bits (the SCAN queue comes before the JACOBI queue in the
+    group order), a histogram of the scan, and an independent reduction
+    beside them at level 0."""
+    import torch
+
+    say("jacobi -> scan -> hist dependency, reduce beside")
+    ny, nx = 300, 517
+    n = ny * nx
+    u = synth.uniform_f32(0xD6, n).reshape(ny, nx)
+    ut = dev(u)
+    v = torch.empty_like(ut)
+    y = torch.empty((n,), dtype=torch.int32, device="cuda")
+    h = torch.full((256,), 5, dtype=torch.int32, device="cuda")
+    r_in = synth.uniform_int32(0xD7, 70001, -1000, 1000)
+    r_x = dev(r_in)
+    r = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    items = [(spmd.JACOBI5_F32, nx, ny, 256, ut, v), (spmd.SCAN_I32, n, 1, 256, v.view(torch.int32), y),
+             (spmd.HIST256_U32, n, 1, 256, y, h), (spmd.REDUCE_I32, r_in.size, 1, 256, r_x, r)]
+    sched = [(256, 2, 4), (256, 8, 1), (256, 16, 4), (256, 4, 2)]
+    b = spmd.batch.Batch(items, sched, deps=[None, 0, 1, None])
+    want_v = oracle.jacobi5_f32(u, 16, 16)
+    want_y = oracle.scan_i32(want_v.view(np.int32).ravel(), 64, 4)
+    want_h = oracle.hist256_u32(want_y.view(np.uint32), 1, 64)
+    want_r = int(oracle.reduce_i32(r_in, 1, 64)[1])
+    for mode in ("eager", "graph", "graph"):
+        v.fill_(-1.0)
+        y.fill_(0)
+        r.fill_(7)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        assert np.array_equal(host(v), want_v), mode
+        assert np.array_equal(host(y), want_y), mode
+        assert np.array_equal(host(h).view(np.uint32), want_h), mode
+        assert int(host(r)[0]) == want_r, mode
     b.close()
