@@ -112,7 +112,7 @@ def main():
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
                     help="run only the fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
-    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain"), default=None,
+    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain", "hist"), default=None,
                     help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
     ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
@@ -135,7 +135,7 @@ def main():
         return
     if args.only:
         fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads,
-              "chain": chain_workloads}[args.only]
+              "chain": chain_workloads, "hist": hist_contention_workloads}[args.only]
         out = fn(spmd, synth)
         calibration_copies()
         print(json.dumps({f"only_{args.only}": out}), flush=True)
@@ -285,6 +285,7 @@ def extra_workloads(spmd, synth):
     res = copy_reference()
     res.update(reduce_workloads(spmd, synth))
     res.update(jacobi_workloads(spmd, synth))
+    res.update(hist_contention_workloads(spmd, synth))
     res.update(compact_workloads(spmd, synth))
     res.update(chain_workloads(spmd, synth))
     res.update(gemm_workloads(spmd, synth))
@@ -467,6 +468,41 @@ def chain_workloads(spmd, synth):
         res[f"jacobi chain {nn}^2 x {sweeps} sweeps"] = rec
         del bufs, u0
         torch.cuda.empty_cache()
+    return res
+
+
+def hist_contention_workloads(spmd, synth):
+    """The histogram at the step's shape (2^27 keys, grid 256, block 1024)
+    under LDS-atomic contention: bounded Zipf exponents 0 (uniform) to 3,
+    hot bins in place or sent through the seeded bin permutation, and every
+    key in one bin."""
+    import torch
+
+    from paper_2206_07896_amd import batch as B
+
+    n = HIST_N
+    keys = torch.empty(n, dtype=torch.int32, device="cuda")
+    hist = torch.empty(256, dtype=torch.int32, device="cuda")
+    perm = torch.from_numpy(synth.bin_permutation().astype(np.int32)).cuda()
+    res = {}
+    for alpha in (0.0, 1.1, 2.0, 3.0, "one"):
+        for permuted in ((False, True) if alpha != "one" else (False,)):
+            if alpha == "one":
+                keys.fill_(7)
+            else:
+                cdf = torch.from_numpy(synth.zipf_cdf(alpha, 256)).cuda()
+                B.synth_zipf_u32(keys, synth.SEED_HIST, cdf)
+                if permuted:
+                    keys.copy_(perm[keys.long()])
+            torch.cuda.synchronize()
+            ms = measure(lambda: spmd.ops.hist256_u32(keys, HIST_GRID, HIST_BLOCK, hist=hist), 10, warmup=3)
+            assert int(hist.cpu().numpy().view(np.uint32).astype(np.int64).sum()) == n
+            name = "one bin" if alpha == "one" else f"zipf{alpha}" + (" permuted" if permuted else "")
+            gbs = 4 * n / ms / 1e6
+            res[f"hist256_u32 2^27 {name} g{HIST_GRID} b{HIST_BLOCK}"] = {
+                "us": round(ms * 1e3, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    del keys
+    torch.cuda.empty_cache()
     return res
 
 

@@ -26,7 +26,11 @@ Derived distributions:
 * bounded Zipf(alpha) over ranks ``1..K``: inverse CDF in fp64 on
   ``u = (h >> 11) * 2^-53``; rank ``r`` becomes key ``r - 1``;
 * N(0, 1): Box-Muller in fp64 from two stream elements (indices ``2i`` and
-  ``2i + 1``), rounded to fp32.
+  ``2i + 1``), rounded to fp32;
+* a seeded permutation of the 256 histogram bins (Fisher-Yates, swap
+  partner of position ``j`` from 256 down to 2: Lemire's multiply-shift of
+  element ``256 - j`` onto ``[0, j)``), so that a skewed law's hot bins land
+  at scattered bins rather than 0, 1, 2, ...
 """
 
 from __future__ import annotations
@@ -46,6 +50,7 @@ SEED_GEMM = 0xC3B
 SEED_BATCH = 0xC4
 SEED_TRAIN = 0xC5
 SEED_HELDOUT = 0xC5F
+SEED_BIN_PERM = 0xC2C
 
 _CHUNK = 1 << 22
 
@@ -146,3 +151,19 @@ def uniform_u32(seed: int, count: int, start: int = 0) -> np.ndarray:
 def uniform_unit_f64(seed: int, count: int, start: int = 0) -> np.ndarray:
     """fp64 uniform on [0, 1): the top 53 bits of each hash times 2^-53."""
     return (hashes(seed, start, count) >> np.uint64(11)).astype(np.float64) * 2.0**-53
+
+
+def bin_permutation(seed: int = SEED_BIN_PERM, k: int = 256) -> np.ndarray:
+    """A permutation of ``0..k-1`` by Fisher-Yates from the seed's stream."""
+    perm = np.arange(k, dtype=np.uint32)
+    h = hashes(seed, 0, k)
+    for j in range(k, 1, -1):
+        r = int(((int(h[k - j]) >> 32) * j) >> 32)
+        perm[j - 1], perm[r] = perm[r], perm[j - 1]
+    return perm
+
+
+def permute_bins(keys: np.ndarray, perm: np.ndarray) -> np.ndarray:
+    """Keys with their low byte (the bin) sent through ``perm``."""
+    keys = np.asarray(keys, dtype=np.uint32)
+    return (keys & np.uint32(0xFFFFFF00)) | perm[keys & np.uint32(255)]

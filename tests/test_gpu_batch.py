@@ -236,6 +236,34 @@ def test_mixed_workload_small(spmd):
     b.close()
 
 
+def test_batch_hist_skew(spmd):
+    """Skewed and one-bin histogram instances through the queue's fused
+    chunk body under several schedules."""
+    import torch
+
+    perm = synth.bin_permutation()
+    insts = []
+    for i, (alpha, n, sched) in enumerate([(0.0, 100003, (256, 4, 8)), (2.0, 1 << 18, (512, 16, 1)),
+                                           (3.0, 262147, (64, 1, 32)), ("one", 50000, (128, 8, 3)),
+                                           (2.0, 1 << 18, (1024 // 4, 16, 32)), (3.0, 4099, (512, 2, 2))]):
+        upper = synth.uniform_u32(70 + i, n) & np.uint32(0xFFFFFF00)
+        if alpha == "one":
+            x = upper | np.uint32(200)
+        else:
+            x = synth.permute_bins(synth.zipf_u32(60 + i, n, alpha) | upper, perm) if i % 2 else \
+                synth.zipf_u32(60 + i, n, alpha) | upper
+        insts.append(dict(kind="hist", kid=spmd.HIST256_U32, n=n, ny=1, x=x, tin=dev(x),
+                          tout=torch.full((256,), 77, dtype=torch.int32, device="cuda"), bd=256, sched=sched))
+    say("batch hist skew", [it["sched"] for it in insts])
+    b = spmd.batch.Batch(items_of(insts), [it["sched"] for it in insts])
+    for mode in ("eager", "graph", "graph"):
+        scribble(insts)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        check_all(insts, f"hist skew {mode}")
+    b.close()
+
+
 @pytest.mark.parametrize("seed", [5])
 def test_batch_random_levels(spmd, seed):
     """Seeded instances with random dependencies (no data flows along them):

@@ -162,6 +162,40 @@ def test_hist(spmd, n, grid, block):
         assert np.array_equal(host(h, np.uint32), want), rep
 
 
+def skewed_keys(n, alpha, perm, seed):
+    """Bounded Zipf(alpha) bins (or every key in bin 7 for alpha "one"),
+    optionally through the seeded bin permutation, random upper bits."""
+    upper = synth.uniform_u32(seed + 1, n) & np.uint32(0xFFFFFF00)
+    if alpha == "one":
+        return upper | np.uint32(7)
+    keys = synth.zipf_u32(seed, n, alpha) | upper
+    return synth.permute_bins(keys, synth.bin_permutation()) if perm else keys
+
+
+@pytest.mark.parametrize("alpha,perm", [(0.0, False), (1.1, True), (1.5, False), (2.0, True), (3.0, False),
+                                        ("one", False)])
+@pytest.mark.parametrize("n,grid,block,offset", [((1 << 20) + 13, 256, 1024, 0), (300007, 7, 64, 1),
+                                                 (1 << 16, 1024, 512, 0), (4099, 2, 256, 0)])
+def test_hist_skew(spmd, alpha, perm, n, grid, block, offset):
+    """Contention: skewed and one-bin keys, hot bins in place or permuted,
+    16-byte aligned (vote path) and offset by one key (plain path)."""
+    say("hist skew", alpha, perm, n, grid, block, offset)
+    keys = skewed_keys(n + offset, alpha, perm, 0x51 + n)
+    want = oracle.hist256_u32(keys[offset:], grid, block)
+    h = spmd.ops.hist256_u32(dev(keys)[offset:], grid, block)
+    spmd.sync()
+    assert np.array_equal(host(h, np.uint32), want)
+
+
+def test_hist_skew_workload_size(spmd):
+    n = 1 << 27
+    say("hist 2^27 zipf3 permuted, 256 x 1024")
+    keys = skewed_keys(n, 3.0, True, synth.SEED_HIST)
+    h = spmd.ops.hist256_u32(dev(keys), 256, 1024)
+    spmd.sync()
+    assert np.array_equal(host(h, np.uint32), oracle.hist256_u32(keys, 256, 1024, pool=16))
+
+
 def test_hist_workload_size(spmd):
     n = 1 << 27
     say("hist 2^27 zipf")

@@ -49,6 +49,29 @@ def test_zipf_generator_matches_its_distribution():
     assert abs(p[:8].sum() - 0.519) < 5e-3
 
 
+@pytest.mark.parametrize("alpha,p0", [(0.0, 1 / 256), (2.0, 1 / (np.pi**2 / 6 - 1 / 256.5)), (3.0, 0.8319)])
+def test_zipf_exponents_match_closed_forms(alpha, p0):
+    # p_0 = 1 / H_{256,alpha}: 1/256 for the uniform law; H_{256,2} is
+    # zeta(2) = pi^2/6 less its tail beyond 256, about 1/256.5; H_{256,3} =
+    # 1.2020 (zeta(3) = 1.20206 less a tail below 1e-5).
+    assert abs(1.0 / np.sum(1.0 / np.arange(1, 257) ** alpha) - p0) < 1e-4
+    n = 1 << 20
+    keys = synth.zipf_u32(synth.SEED_HIST, n, alpha)
+    got = np.count_nonzero(keys == 0) / n
+    assert abs(got - p0) < 5 * np.sqrt(p0 * (1 - p0) / n) + 1e-9
+
+
+def test_bin_permutation_is_a_bijection_and_relabels_the_histogram():
+    perm = synth.bin_permutation()
+    assert sorted(perm.tolist()) == list(range(256))
+    assert int(np.count_nonzero(perm == np.arange(256))) < 8  # not near the identity
+    keys = synth.zipf_u32(5, 70001, 2.0) ^ (synth.uniform_u32(6, 70001) & np.uint32(0xFFFFFF00))
+    moved = synth.permute_bins(keys, perm)
+    assert np.array_equal(moved >> 8, keys >> 8)
+    h, hm = oracle.hist256_u32(keys, 3, 64), oracle.hist256_u32(moved, 3, 64)
+    assert np.array_equal(hm[perm], h)  # bin b's count moves to bin perm[b]
+
+
 # --------------------------------------------------------------------------
 # runtime: the paper's worked fetch examples
 # --------------------------------------------------------------------------
