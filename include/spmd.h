@@ -160,10 +160,26 @@ enum {
      * spmd_workspace_size() bytes,
      * 16-byte aligned, zero-filled before first use, then reusable as for
      * SCAN.  y must hold n elements. */
-    SPMD_COMPACT_I32 = 8
+    SPMD_COMPACT_I32 = 8,
+
+    /* S fused sweeps of the SPMD_JACOBI5_F32 stencil in one pass over HBM
+     * (temporal blocking; the roofline discussion of Section VI-B: a
+     * one-sweep stencil is bound by memory, so more sweeps per byte moved
+     * is the way past that bound).  u_next = S sweeps of u, every cell
+     * computed exactly as by S one-sweep launches (bit-identical).  Each
+     * workgroup holds a 256-column region -- a (256 - 2H) x 64 interior
+     * tile plus a halo of H = 4 cells (S <= 4) or H = 8 cells (S <= 8) --
+     * in registers, sweeps there, and stores the interior.
+     * args: const float* u, float* u_next, uint32_t nx, uint32_t ny,
+     *       uint32_t sweeps (S, 1..8)
+     * block (256,1,1); grid (GX,GY,1) with GX*(256 - 2H) >= nx and
+     * GY*64 >= ny.
+     * nx must be a multiple of 4, u and u_next 16-byte aligned and not
+     * overlapping (SPMD_ERR_ARGS otherwise). */
+    SPMD_JACOBI5T_F32 = 9
 };
 
-#define SPMD_NUM_KERNELS 8
+#define SPMD_NUM_KERNELS 9
 #define SPMD_WARPTEST_NCASES 904
 
 /* Launch one grid of kernel class `kernel_id` on `stream` (Section IV, "Push

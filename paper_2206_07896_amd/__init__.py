@@ -51,7 +51,8 @@ GEMM_F32 = 5
 WARPTEST = 6
 REVERSE_I32 = 7
 COMPACT_I32 = 8
-NUM_KERNELS = 8
+JACOBI5T_F32 = 9
+NUM_KERNELS = 9
 WARPTEST_NCASES = 904
 KERNELS = {}
 

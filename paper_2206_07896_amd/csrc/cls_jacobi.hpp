@@ -76,6 +76,18 @@ __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float*
 }
 
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2.  Tile t of XCD x = id mod 8 is the (id / 8)-th of a
+// contiguous range of tiles, so neighbouring tiles -- which read each
+// other's edge lines as halo -- run on the same XCD and share its L2.
+constexpr uint32_t NUM_XCD = 8;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t nt) {
+    const uint32_t q = nt / NUM_XCD, r = nt % NUM_XCD;
+    const uint32_t x = id % NUM_XCD, local = id / NUM_XCD;
+    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
 // Vector form, for nx a multiple of 4 and 16-byte aligned rows: a workgroup
 // of 64 x BY threads owns 256 columns and BY*C rows, each thread four
 // consecutive columns (one 16-byte load or store per row) and C rows, BY

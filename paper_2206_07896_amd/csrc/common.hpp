@@ -75,6 +75,7 @@ int launch_gemm_f32(const LaunchCtx& c);
 int launch_warptest(const LaunchCtx& c);
 int launch_reverse_i32(const LaunchCtx& c);
 int launch_compact_i32(const LaunchCtx& c);
+int launch_jacobi5t_f32(const LaunchCtx& c);
 
 size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3 block, uint64_t n);
 

@@ -10,18 +10,6 @@ __global__ __launch_bounds__(BX* BY) void jacobi5_kernel(const float* __restrict
     jacobi_block<BX, BY, C>(u, v, nx, ny, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, L);
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
-// has its own L2.  Tile t of XCD x = id mod 8 is the (id / 8)-th of a
-// contiguous range of tiles, so neighbouring tiles -- which read each
-// other's edge lines as halo -- run on the same XCD and share its L2.
-constexpr uint32_t NUM_XCD = 8;
-
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t nt) {
-    const uint32_t q = nt / NUM_XCD, r = nt % NUM_XCD;
-    const uint32_t x = id % NUM_XCD, local = id / NUM_XCD;
-    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
 template <int BY, int C>
 __global__ __launch_bounds__(64 * BY) void jacobi5_v4_kernel(const float* __restrict__ u, float* __restrict__ v,
                                                              uint32_t nx, uint32_t ny) {

@@ -49,6 +49,7 @@ const ClassInfo kClasses[SPMD_NUM_KERNELS + 1] = {
     {"warptest", "ppp", launch_warptest, ws_none},
     {"reverse_i32", "pu", launch_reverse_i32, ws_none},
     {"compact_i32", "pppuup", launch_compact_i32, ws_compact_i32},
+    {"jacobi5t_f32", "ppuuu", launch_jacobi5t_f32, ws_none},
 };
 
 const ClassInfo* class_info(int id) {

@@ -8,8 +8,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (COMPACT_I32, GEMM_F32, HIST256_U32, JACOBI5_F32, REDUCE_I32, REVERSE_I32, SCAN_I32, WARPTEST,
-               WARPTEST_NCASES, launch, workspace_size)
+from . import (COMPACT_I32, GEMM_F32, HIST256_U32, JACOBI5_F32, JACOBI5T_F32, REDUCE_I32, REVERSE_I32, SCAN_I32,
+               WARPTEST, WARPTEST_NCASES, launch, workspace_size)
 
 
 def _cdiv(a: int, b: int) -> int:
@@ -112,6 +112,38 @@ def jacobi5_sweeps(u: torch.Tensor, sweeps: int, block=(16, 16), cells: int = 1,
     for _ in range(sweeps):
         jacobi5_f32(src, dst, block, cells, stream)
         src, dst = dst, src
+    return src
+
+
+def jacobi5t_grid(nx: int, ny: int, sweeps: int):
+    """Grid of the fused-sweep class: (256 - 2H) x 64 interior tiles, halo
+    H = 4 for up to 4 sweeps, else 8."""
+    h = 4 if sweeps <= 4 else 8
+    return (_cdiv(nx, 256 - 2 * h), _cdiv(ny, 64))
+
+
+def jacobi5t_f32(u: torch.Tensor, sweeps: int, out=None, stream=None):
+    """``sweeps`` (1..8) sweeps in one launch (SPMD_JACOBI5T_F32)."""
+    _check_dev(u)
+    ny, nx = u.shape
+    if out is None:
+        out = torch.empty_like(u)
+    launch(JACOBI5T_F32, jacobi5t_grid(nx, ny, sweeps), (256, 1, 1), 0, [u, out, nx, ny, sweeps], stream)
+    return out
+
+
+def jacobi5t_sweeps(u: torch.Tensor, sweeps: int, per_launch: int = 4, scratch=None, stream=None):
+    """``sweeps`` sweeps as launches of up to ``per_launch`` fused sweeps,
+    ping-ponging between a copy of u and a second buffer."""
+    a = u.clone() if sweeps else u
+    b = torch.empty_like(u) if scratch is None else scratch
+    src, dst = a, b
+    left = sweeps
+    while left:
+        k = min(per_launch, left)
+        jacobi5t_f32(src, k, dst, stream)
+        src, dst = dst, src
+        left -= k
     return src
 
 

@@ -45,8 +45,9 @@ def test_signatures_and_names(spmd):
     assert spmd.signature(spmd.WARPTEST) == "ppp"
     assert spmd.signature(spmd.REVERSE_I32) == "pu"
     assert spmd.signature(spmd.COMPACT_I32) == "pppuup"
+    assert spmd.signature(spmd.JACOBI5T_F32) == "ppuuu"
     assert set(spmd.KERNELS) == {"reduce_i32", "scan_i32", "hist256_u32", "jacobi5_f32", "gemm_f32", "warptest",
-                                 "reverse_i32", "compact_i32"}
+                                 "reverse_i32", "compact_i32", "jacobi5t_f32"}
     lib = spmd.lib()
     assert lib.spmd_kernel_signature(0) is None
     assert lib.spmd_kernel_signature(spmd.NUM_KERNELS + 1) is None
@@ -74,7 +75,7 @@ def _raw_launch(spmd, kid, grid, block, shm, args):
     return spmd.lib().spmd_launch(kid, spmd._dim3(grid), spmd._dim3(block), shm, argp, None)
 
 
-@pytest.mark.parametrize("kid", [0, -3, 9, 1000])
+@pytest.mark.parametrize("kid", [0, -3, 10, 1000])
 def test_unknown_kernel(spmd, kid):
     assert _raw_launch(spmd, kid, 1, 64, 0, None) == -1
 

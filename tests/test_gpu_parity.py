@@ -246,7 +246,60 @@ def test_jacobi_workload_size(spmd):
     ref64 = oracle.jacobi5_f64(u, sweeps)
     rel = np.abs(got.astype(np.float64) - ref64) / np.abs(ref64)
     assert rel.max() <= 1e-6, rel.max()
-    assert np.array_equal(got, oracle.jacobi5_f32_sweeps(u, sweeps))
+    want = oracle.jacobi5_f32_sweeps(u, sweeps)
+    assert np.array_equal(got, want)
+    for per in (4, 8):  # the fused-sweep class: 25 launches of 4, or 12 of 8 and one of 4
+        say("jacobi 8192^2 x 100 fused", per)
+        got = host(spmd.ops.jacobi5t_sweeps(dev(u), sweeps, per_launch=per))
+        spmd.sync()
+        assert np.array_equal(got, want), per
+
+
+# --------------------------------------------------------------------------
+# JACOBI5T: fused sweeps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sweeps", [1, 2, 3, 4, 5, 8])
+def test_jacobi_fused_bit_exact(spmd, sweeps):
+    """S sweeps in one launch equal S sweeps of the oracle, on grids that
+    are smaller than, equal to and ragged against the 128 x 64 tile."""
+    for (ny, nx) in [(1, 4), (2, 8), (3, 4), (5, 12), (64, 128), (65, 132), (131, 516), (200, 260), (63, 1028)]:
+        say("jacobi fused", sweeps, ny, nx)
+        u = synth.uniform_f32(0x5EED + nx * 7 + ny, ny * nx).reshape(ny, nx)
+        got = host(spmd.ops.jacobi5t_f32(dev(u), sweeps))
+        spmd.sync()
+        assert np.array_equal(got, oracle.jacobi5_f32_sweeps(u, sweeps)), (ny, nx)
+
+
+def test_jacobi_fused_chain_and_closed_form(spmd):
+    """27 sweeps as 8 + 8 + 8 + 3 fused launches against the oracle, and the
+    linear field u = i + 2j, a fixed point of the stencil, through 8."""
+    ny, nx = 300, 1028
+    u = synth.uniform_f32(0xF00D, ny * nx).reshape(ny, nx)
+    got = host(spmd.ops.jacobi5t_sweeps(dev(u), 27, per_launch=8))
+    spmd.sync()
+    assert np.array_equal(got, oracle.jacobi5_f32_sweeps(u, 27))
+    i, j = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    lin = (i + 2 * j).astype(np.float32)
+    got = host(spmd.ops.jacobi5t_f32(dev(lin), 8))
+    spmd.sync()
+    assert np.array_equal(got, lin)
+
+
+def test_jacobi_fused_rejects_bad_launches(spmd):
+    import torch
+
+    u = dev(np.zeros((64, 128), np.float32))
+    v = torch.empty_like(u)
+    ok = ((1, 1, 1), (256, 1, 1))
+    for args, grid, block, kind in [([u, v, 128, 64, 0], *ok, "ARGS"), ([u, v, 128, 64, 9], *ok, "ARGS"),
+                                    ([u, v, 126, 64, 2], *ok, "ARGS"), ([u, u, 128, 64, 2], *ok, "ARGS"),
+                                    ([u, v, 128, 64, 2], (1, 1, 1), (128, 1, 1), "INVALID_DIM"),
+                                    ([u, v, 256, 32, 2], *ok, "INVALID_DIM"),  # 248 columns per tile
+                                    ([u.view(-1)[1:], v, 124, 64, 2], *ok, "ARGS")]:
+        with pytest.raises(spmd.SpmdError) as e:
+            spmd.launch(spmd.JACOBI5T_F32, grid, block, 0, args)
+        assert e.value.kind == kind, (args[2:], grid, block)
 
 
 # --------------------------------------------------------------------------
