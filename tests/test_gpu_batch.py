@@ -289,14 +289,16 @@ def test_batch_random_levels(spmd, seed):
 # Dependent instances (spmd_batch_create_dep)
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("nx", [517, 516])
 @pytest.mark.parametrize("sched", [(256, 4, 8), (64, 1, 3), (512, 8, 32), (256, 4, 0), (128, 2, 0)])
-def test_dependent_jacobi_chain_in_one_batch(spmd, sched):
-    """25 sweeps as 25 instances of one queue, each reading the previous
-    one's output: one batch, one launch per queue, bit-exact against 25
-    sweeps of the oracle, eagerly and over graph replays."""
+def test_dependent_jacobi_chain_in_one_batch(spmd, sched, nx):
+    """25 sweeps as 25 instances of one batch, each reading the previous
+    one's output (nx 516 also takes the 16-byte body when a sweep runs as its
+    own grid), bit-exact against 25 sweeps of the oracle, eagerly and over
+    graph replays."""
     import torch
 
-    ny, nx, sweeps = 131, 517, 25
+    ny, sweeps = 131, 25
     say("dependent jacobi chain", ny, nx, sweeps, sched)
     u = synth.uniform_f32(0xD5, ny * nx).reshape(ny, nx)
     bufs = [dev(u), torch.empty((ny, nx), dtype=torch.float32, device="cuda")]
