@@ -515,6 +515,8 @@ def hist_contention_workloads(spmd, synth):
     hist = torch.empty(256, dtype=torch.int32, device="cuda")
     perm = torch.from_numpy(synth.bin_permutation().astype(np.int32)).cuda()
     res = {}
+    keys.zero_()
+    measure(lambda: spmd.ops.hist256_u32(keys, HIST_GRID, HIST_BLOCK, hist=hist), 10, warmup=5)  # settle clocks
     for alpha in (0.0, 1.1, 2.0, 3.0, "one"):
         for permuted in ((False, True) if alpha != "one" else (False,)):
             if alpha == "one":
@@ -529,7 +531,7 @@ def hist_contention_workloads(spmd, synth):
             assert int(hist.cpu().numpy().view(np.uint32).astype(np.int64).sum()) == n
             name = "one bin" if alpha == "one" else f"zipf{alpha}" + (" permuted" if permuted else "")
             gbs = 4 * n / ms / 1e6
-            res[f"hist256_u32 2^27 {name} g{HIST_GRID} b{HIST_BLOCK}"] = {
+            res[f"hist contention: hist256_u32 2^27 {name} g{HIST_GRID} b{HIST_BLOCK}"] = {
                 "us": round(ms * 1e3, 2), "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     del keys
     torch.cuda.empty_cache()
