@@ -117,7 +117,8 @@ enum {
      * args: const float* A, const float* B, float* C, uint32_t M,
      *       uint32_t N, uint32_t K
      * block (256,1,1); grid (GX,GY,1); the tile edge T is the smallest of
-     * {64, 128} with GX*T >= N and GY*T >= M. */
+     * {64, 128, 256} with GX*T >= N and GY*T >= M (at 256 each wave holds
+     * a 128 x 128 block of C in accumulator registers, one wave per SIMD). */
     SPMD_GEMM_F32 = 5,
 
     /* Conformance of the 32-lane warp operations on half-wavefronts.

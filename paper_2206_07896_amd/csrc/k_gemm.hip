@@ -21,7 +21,7 @@ int launch_gemm_f32(const LaunchCtx& c) {
     auto K = arg<uint32_t>(c.args, 5);
     if (!A || !B || !C || M == 0 || N == 0 || K == 0) return SPMD_ERR_ARGS;
     int T = 0;
-    for (int t : {64, 128})
+    for (int t : {64, 128, 256})
         if ((uint64_t)c.grid.x * t >= N && (uint64_t)c.grid.y * t >= M) {
             T = t;
             break;
@@ -32,8 +32,10 @@ int launch_gemm_f32(const LaunchCtx& c) {
     dim3 g(c.grid.x, c.grid.y), b(256);
     if (T == 64)
         hipLaunchKernelGGL(gemm_f32_kernel<64>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
-    else
+    else if (T == 128)
         hipLaunchKernelGGL(gemm_f32_kernel<128>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+    else  // 128 x 128 per wave: 256 accumulators in AGPRs, one wave per SIMD
+        hipLaunchKernelGGL(gemm_f32_kernel<256>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }

@@ -310,7 +310,7 @@ def _gemm_gate(C, c64, K):
     return np.abs(C.astype(np.float64) - c64).max() / np.abs(c64).max() <= 1e-5 * np.sqrt(K)
 
 
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [64, 128, 256])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 64, 16), (65, 63, 17), (128, 96, 130), (3, 200, 5), (257, 130, 64),
                                    (512, 512, 512)])
 def test_gemm_shapes(spmd, tile, M, N, K):
@@ -326,7 +326,7 @@ def test_gemm_shapes(spmd, tile, M, N, K):
     assert np.all(np.abs(C - c64) <= bound + 1e-30)
 
 
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [64, 128, 256])
 def test_gemm_exact_cases(spmd, tile):
     say("gemm exact", tile)
     rng = np.random.default_rng(7)
@@ -341,7 +341,7 @@ def test_gemm_exact_cases(spmd, tile):
     assert np.array_equal(C2, A2)
 
 
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [64, 128, 256])
 def test_gemm_workload_size(spmd, tile):
     n = 4096
     say("gemm 4096^3", tile)
