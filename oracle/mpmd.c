@@ -317,9 +317,13 @@ static int run_block(ox_ctx *c, const ox_launch *L, uint64_t lin) {
     b->linear_bid = lin;
     b->region_counter = 0;
     memset(b->u, 0, sizeof b->u);
-    /* fresh, undefined shared memory and registers */
-    memset(b->shm, POISON, b->shm_bytes);
-    memset(b->shm_w, 0, b->shm_bytes);
+    /* fresh, undefined shared memory and registers (a launch without shared
+     * memory has no buffer: memset of a null pointer is undefined even for
+     * zero bytes) */
+    if (b->shm_bytes) {
+        memset(b->shm, POISON, b->shm_bytes);
+        memset(b->shm_w, 0, b->shm_bytes);
+    }
     memset(b->reg, 0xCD, (uint64_t)b->nthreads * b->nreg * sizeof(uint64_t));
     L->body(b);
     return b->err;
