@@ -111,8 +111,8 @@ def main():
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
-                    help="run only the fp32 GEMM at tiles 64 and 128, a few launches each (for profiler runs)")
-    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain", "hist"), default=None,
+                    help="run only the fp32 GEMM at tiles 64, 128 and 256, a few launches each (for profiler runs)")
+    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain", "hist", "mixed"), default=None,
                     help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
     ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
@@ -135,7 +135,8 @@ def main():
         return
     if args.only:
         fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads,
-              "chain": chain_workloads, "hist": hist_contention_workloads}[args.only]
+              "chain": chain_workloads, "hist": hist_contention_workloads,
+              "mixed": lambda sp, _sy: mixed_queue(sp, args.mixed_count, reps=3)}[args.only]
         out = fn(spmd, synth)
         calibration_copies()
         print(json.dumps({f"only_{args.only}": out}), flush=True)
