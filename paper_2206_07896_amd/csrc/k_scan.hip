@@ -2,52 +2,87 @@
 //
 // Workspace (zero-filled once): a 64-bit ticket word (epoch << 32 | count)
 // alone on its cache line, then from byte 256 one u64 status word per
-// tile.  A block takes its tile index from the ticket when it starts, so
-// tiles start in index order and a tile only waits for tiles that started
-// before it: every wait ends.  The ticket's high half is the launch's epoch,
-// the tag of its status words; the block that draws count G-1 -- every
-// block of the launch has drawn by then -- re-arms the count and advances
-// the epoch.  One atomic per tile, nothing to clear between launches.
+// tile.  Tiles are handed out by the ticket, so they start in index order
+// and a tile only waits for tiles that a running block already holds: every
+// wait ends.  The ticket's high half is the launch's epoch, the tag of its
+// status words.
+//
+// The kernel is persistent: P = min(G, resident blocks) blocks loop over the
+// G tiles.  A block draws its next ticket as soon as its current tile has
+// published its inclusive prefix (no tile can wait on it any more), so the
+// draw's round trip overlaps the tile's stores and the next tile starts
+// without a workgroup launch.  A draw >= G ends the block; each block makes
+// exactly one such draw, so the launch makes G + P draws in all, and the
+// block that makes the last one re-arms the count and advances the epoch.
+// One atomic per tile plus one per block, nothing to clear between
+// launches.
+#include <algorithm>
+
 #include "cls_scan.hpp"
 
 namespace spmd {
 
 constexpr size_t SCAN_WS_HEADER = 256;
 
+// Draw a ticket (thread 0): the tile index, or a value >= ntiles to stop.
+__device__ __forceinline__ uint32_t scan_draw(uint64_t* ticket, uint32_t ntiles, uint32_t* tag) {
+    const uint64_t tk = atomic_add_dev64(ticket, 1ull);
+    const uint32_t count = (uint32_t)tk, epoch = (uint32_t)(tk >> 32);
+    if (count == ntiles + gridDim.x - 1u)  // the launch's last draw
+        __hip_atomic_store(ticket, (uint64_t)(epoch + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *tag = epoch;
+    return count;
+}
+
 template <int B, int I>
 __global__ __launch_bounds__(B) void scan_i32_kernel(const int32_t* __restrict__ x, int32_t* __restrict__ y,
-                                                      uint32_t n, uint32_t* ws, uint32_t* err, bool vec) {
+                                                      uint32_t n, uint32_t ntiles, uint32_t* ws, uint32_t* err,
+                                                      bool vec) {
     __shared__ ScanLds<B, I> L;
-    __shared__ uint32_t s_tile, s_tag;
+    __shared__ uint32_t s_tile, s_next, s_tag;
     uint64_t* ticket = reinterpret_cast<uint64_t*>(ws);
     uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + SCAN_WS_HEADER);
-    if (threadIdx.x == 0) {
-        const uint64_t tk = atomic_add_dev64(ticket, 1ull);
-        const uint32_t count = (uint32_t)tk, epoch = (uint32_t)(tk >> 32);
-        if (count == gridDim.x - 1u)
-            __hip_atomic_store(ticket, (uint64_t)(epoch + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_tile = count;
-        s_tag = epoch;
-    }
+    if (threadIdx.x == 0) s_tile = scan_draw(ticket, ntiles, &s_tag);
     __syncthreads();
-    scan_tile<B, I>(x, y, n, s_tile, status, s_tag, err, vec, L);
+    uint32_t tile = s_tile;
+    const uint32_t tag = s_tag;  // every draw of a launch carries its epoch
+    while (tile < ntiles) {
+        auto draw_next = [&]() {
+            uint32_t unused;
+            s_next = scan_draw(ticket, ntiles, &unused);
+        };
+        scan_tile<B, I>(x, y, n, tile, status, tag, err, vec, L, draw_next);
+        __syncthreads();  // s_next is written; the LDS area is free again
+        tile = s_next;
+    }
 }
 
 size_t ws_scan_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return SCAN_WS_HEADER + 8ull * grid.x; }
 
+// Persistent grid for G tiles: at most the blocks that are resident at once.
+template <int B, int I>
+static void launch_bi(uint32_t G, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t n,
+                      uint32_t* ws, uint32_t* err, bool vec, int num_cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, scan_i32_kernel<B, I>, B, dyn) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const uint32_t P = (uint32_t)std::min<uint64_t>(G, (uint64_t)per_cu * (uint64_t)num_cus);
+    hipLaunchKernelGGL((scan_i32_kernel<B, I>), dim3(P), dim3(B), dyn, s, x, y, n, G, ws, err, vec);
+}
+
 template <int B>
-static void launch_b(uint32_t I, dim3 g, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t n,
-                     uint32_t* ws, uint32_t* err, bool vec) {
-    dim3 b(B);
+static void launch_b(uint32_t I, uint32_t G, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t n,
+                     uint32_t* ws, uint32_t* err, bool vec, int num_cus) {
     switch (I) {
-    case 1: hipLaunchKernelGGL((scan_i32_kernel<B, 1>), g, b, dyn, s, x, y, n, ws, err, vec); break;
-    case 2: hipLaunchKernelGGL((scan_i32_kernel<B, 2>), g, b, dyn, s, x, y, n, ws, err, vec); break;
-    case 4: hipLaunchKernelGGL((scan_i32_kernel<B, 4>), g, b, dyn, s, x, y, n, ws, err, vec); break;
-    case 8: hipLaunchKernelGGL((scan_i32_kernel<B, 8>), g, b, dyn, s, x, y, n, ws, err, vec); break;
-    case 16: hipLaunchKernelGGL((scan_i32_kernel<B, 16>), g, b, dyn, s, x, y, n, ws, err, vec); break;
-    case 32: hipLaunchKernelGGL((scan_i32_kernel<B, 32>), g, b, dyn, s, x, y, n, ws, err, vec); break;
+    case 1: launch_bi<B, 1>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
+    case 2: launch_bi<B, 2>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
+    case 4: launch_bi<B, 4>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
+    case 8: launch_bi<B, 8>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
+    case 16: launch_bi<B, 16>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
+    case 32: launch_bi<B, 32>(G, dyn, s, x, y, n, ws, err, vec, num_cus); break;
     case 64:
-        if constexpr (B <= 512) hipLaunchKernelGGL((scan_i32_kernel<B, 64>), g, b, dyn, s, x, y, n, ws, err, vec);
+        if constexpr (B <= 512) launch_bi<B, 64>(G, dyn, s, x, y, n, ws, err, vec, num_cus);
         break;
     }
 }
@@ -68,14 +103,14 @@ int launch_scan_i32(const LaunchCtx& c) {
     if (n == 0) return SPMD_OK;
     const bool vec = aligned(x, 16) && aligned(y, 16);
     const uint32_t G = c.grid.x;
-    dim3 g(G);
     uint32_t* err = c.dev->err_word;
+    const int cus = c.dev->num_cus;
     switch (B) {
-    case 64: launch_b<64>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;
-    case 128: launch_b<128>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;
-    case 256: launch_b<256>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;
-    case 512: launch_b<512>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;
-    case 1024: launch_b<1024>(I, g, c.dyn_shmem, c.stream, x, y, n, ws, err, vec); break;
+    case 64: launch_b<64>(I, G, c.dyn_shmem, c.stream, x, y, n, ws, err, vec, cus); break;
+    case 128: launch_b<128>(I, G, c.dyn_shmem, c.stream, x, y, n, ws, err, vec, cus); break;
+    case 256: launch_b<256>(I, G, c.dyn_shmem, c.stream, x, y, n, ws, err, vec, cus); break;
+    case 512: launch_b<512>(I, G, c.dyn_shmem, c.stream, x, y, n, ws, err, vec, cus); break;
+    case 1024: launch_b<1024>(I, G, c.dyn_shmem, c.stream, x, y, n, ws, err, vec, cus); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
