@@ -359,9 +359,9 @@ def test_gemm_workload_size(spmd, tile):
 
 
 def test_scan_forms_share_a_workspace(spmd):
-    """Small item counts run one workgroup per tile (ticket order), larger
-    ones the persistent cooperative form; both advance the same epoch, so
-    alternating them on one workspace must stay exact."""
+    """Every launch shape (tile size, tile count, resident block count)
+    advances the same epoch and re-arms the ticket at its own last draw, so
+    alternating shapes on one workspace must stay exact."""
     n = 300_007
     say("scan alternating forms", n)
     x = synth.uniform_int32(17, n, -(2**31), 2**31 - 1)
@@ -373,6 +373,43 @@ def test_scan_forms_share_a_workspace(spmd):
         y = spmd.ops.scan_i32(xt, block, items, ws=ws)
         spmd.sync()
         assert np.array_equal(host(y), want), (block, items)
+
+
+def test_scan_graph_replays(spmd):
+    """Three scans of different shapes on one workspace, captured in a graph:
+    replays interleaved with eager scans on the same workspace and host
+    synchronisations, every replay exact."""
+    import torch
+
+    n = 200_003
+    say("scan graph replays", n)
+    x = synth.uniform_int32(23, n, -(2**31), 2**31 - 1)
+    want = oracle.scan_i32(x, 64, 4)
+    xt = dev(x)
+    ws = spmd.ops.workspace(spmd.SCAN_I32, spmd.ops.scan_grid(n, 64, 1), 64, n)
+    ys = [torch.empty_like(xt) for _ in range(3)]
+    shapes = [(512, 64), (256, 8), (1024, 32)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        for (b, i), y in zip(shapes, ys):
+            spmd.ops.scan_i32(xt, b, i, y=y, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    spmd.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for (b, i), y in zip(shapes, ys):
+            spmd.ops.scan_i32(xt, b, i, y=y, ws=ws)
+    for rep in range(3):
+        for y in ys:
+            y.fill_(0)
+        g.replay()
+        spmd.sync()
+        for y in ys:
+            assert np.array_equal(host(y), want), rep
+        e = spmd.ops.scan_i32(xt, 128, 16, ws=ws)  # eager work between replays
+        spmd.sync()
+        assert np.array_equal(host(e), want), rep
 
 
 # --------------------------------------------------------------------------
