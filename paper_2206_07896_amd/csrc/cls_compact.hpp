@@ -58,16 +58,17 @@ __device__ __forceinline__ uint32_t compact_warp_offset(uint32_t run, uint32_t& 
 
 // The stage is complete: the tile's offset in y by look-back (the last
 // tile writes count), then the stage leaves with coalesced stores.
-template <int B, int I>
+template <int B, int I, typename Hook>
 __device__ __forceinline__ void compact_store(int32_t* __restrict__ y, uint32_t* count, uint32_t agg, uint32_t tile,
                                               uint32_t ntiles, uint64_t* status, uint32_t tag, uint32_t* err,
-                                              CompactLds<B, I>& L) {
+                                              CompactLds<B, I>& L, Hook after_lookback) {
     const uint32_t tid = threadIdx.x;
     if (tid < 64) {
         const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
         if (tid == 0) {
             L.excl = excl;
             if (tile == ntiles - 1) *count = excl + agg;
+            after_lookback();
         }
     }
     __syncthreads();  // also orders the stage writes before the reads below
@@ -76,11 +77,11 @@ __device__ __forceinline__ void compact_store(int32_t* __restrict__ y, uint32_t*
 }
 
 // Full, 16-byte aligned tile, I >= 4: rows of 32 lanes x 4 elements.
-template <int B, int I>
+template <int B, int I, typename Hook>
 __device__ __forceinline__ void compact_tile_rows(const int32_t* __restrict__ x, int32_t* __restrict__ y,
                                                   uint32_t* count, int32_t t, uint32_t tile, uint32_t ntiles,
                                                   uint64_t* status, uint32_t tag, uint32_t* err,
-                                                  CompactLds<B, I>& L) {
+                                                  CompactLds<B, I>& L, Hook after_lookback) {
     constexpr int S = I / 4;
     const uint64_t seg = (uint64_t)tile * B * I + (uint64_t)(threadIdx.x >> 5) * 32u * I;
     const u32x4* xv = reinterpret_cast<const u32x4*>(x + seg);
@@ -108,17 +109,17 @@ __device__ __forceinline__ void compact_tile_rows(const int32_t* __restrict__ x,
         for (int j = 0; j < 4; ++j)
             if ((int32_t)v[j] > t) L.stage[p++] = v[j];
     }
-    compact_store<B, I>(y, count, agg, tile, ntiles, status, tag, err, L);
+    compact_store<B, I>(y, count, agg, tile, ntiles, status, tag, err, L, after_lookback);
 }
 
 // Any tile: one element per lane per step, one ballot per step, in two
 // passes over the tile (count, then place), so registers do not grow with
 // I.  Only partial or unaligned tiles take this path.
-template <int B, int I>
+template <int B, int I, typename Hook>
 __device__ __forceinline__ void compact_tile_items(const int32_t* __restrict__ x, int32_t* __restrict__ y,
                                                    uint32_t* count, uint32_t n, int32_t t, uint32_t tile,
                                                    uint32_t ntiles, uint64_t* status, uint32_t tag,
-                                                   uint32_t* err, CompactLds<B, I>& L) {
+                                                   uint32_t* err, CompactLds<B, I>& L, Hook after_lookback) {
     const uint64_t seg = (uint64_t)tile * B * I + (uint64_t)(threadIdx.x >> 5) * 32u * I;
     uint32_t run = 0;
     for (int k = 0; k < I; ++k) {
@@ -136,21 +137,23 @@ __device__ __forceinline__ void compact_tile_items(const int32_t* __restrict__ x
         if (keep) L.stage[p + below(m)] = (uint32_t)v;
         p += (uint32_t)__builtin_popcount(m);
     }
-    compact_store<B, I>(y, count, agg, tile, ntiles, status, tag, err, L);
+    compact_store<B, I>(y, count, agg, tile, ntiles, status, tag, err, L, after_lookback);
 }
 
-template <int B, int I>
+// Thread 0 calls `after_lookback` once the tile's inclusive count is
+// published (no other tile can wait on this one any more).
+template <int B, int I, typename Hook>
 __device__ __forceinline__ void compact_tile(const int32_t* __restrict__ x, int32_t* __restrict__ y,
                                              uint32_t* count, uint32_t n, int32_t t, uint32_t tile,
                                              uint32_t ntiles, uint64_t* status, uint32_t tag, uint32_t* err,
-                                             bool vec, CompactLds<B, I>& L) {
+                                             bool vec, CompactLds<B, I>& L, Hook after_lookback) {
     if constexpr (I >= 4) {
         if (vec && (uint64_t)tile * B * I + (uint64_t)B * I <= (uint64_t)n) {
-            compact_tile_rows<B, I>(x, y, count, t, tile, ntiles, status, tag, err, L);
+            compact_tile_rows<B, I>(x, y, count, t, tile, ntiles, status, tag, err, L, after_lookback);
             return;
         }
     }
-    compact_tile_items<B, I>(x, y, count, n, t, tile, ntiles, status, tag, err, L);
+    compact_tile_items<B, I>(x, y, count, n, t, tile, ntiles, status, tag, err, L, after_lookback);
 }
 
 }  // namespace spmd

@@ -2,50 +2,81 @@
 //
 // Workspace as for SCAN_I32 (zero-filled once): a 64-bit ticket word
 // (epoch << 32 | count) alone on its cache line, then from byte 256 one u64
-// status word per tile.  Tiles take their index from the ticket in start
-// order, so every look-back wait is for a tile that has started; the block
-// that draws the last count re-arms the ticket and advances the epoch.
+// status word per tile.  As for the scan, the kernel is persistent:
+// min(G, resident) blocks take tiles from the ticket in order, so every
+// look-back wait is for a tile a running block holds; a block draws its
+// next tile once its current tile is stored (no workgroup launch between
+// tiles), and the launch's last draw (G + blocks - 1) re-arms the ticket
+// and advances the epoch.
+#include <algorithm>
+
 #include "cls_compact.hpp"
 
 namespace spmd {
 
 constexpr size_t COMPACT_WS_HEADER = 256;
 
+__device__ __forceinline__ uint32_t compact_draw(uint64_t* ticket, uint32_t ntiles, uint32_t* tag) {
+    const uint64_t tk = atomic_add_dev64(ticket, 1ull);
+    const uint32_t cnt = (uint32_t)tk, epoch = (uint32_t)(tk >> 32);
+    if (cnt == ntiles + gridDim.x - 1u)  // the launch's last draw
+        __hip_atomic_store(ticket, (uint64_t)(epoch + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *tag = epoch;
+    return cnt;
+}
+
 template <int B, int I>
 __global__ __launch_bounds__(B) void compact_i32_kernel(const int32_t* __restrict__ x, int32_t* __restrict__ y,
-                                                         uint32_t* count, uint32_t n, int32_t t, uint32_t* ws,
-                                                         uint32_t* err, bool vec) {
+                                                         uint32_t* count, uint32_t n, int32_t t, uint32_t ntiles,
+                                                         uint32_t* ws, uint32_t* err, bool vec) {
     __shared__ CompactLds<B, I> L;
-    __shared__ uint32_t s_tile, s_tag;
+    __shared__ uint32_t s_tile, s_next, s_tag;
     uint64_t* ticket = reinterpret_cast<uint64_t*>(ws);
     uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + COMPACT_WS_HEADER);
-    if (threadIdx.x == 0) {
-        const uint64_t tk = atomic_add_dev64(ticket, 1ull);
-        const uint32_t cnt = (uint32_t)tk, epoch = (uint32_t)(tk >> 32);
-        if (cnt == gridDim.x - 1u)
-            __hip_atomic_store(ticket, (uint64_t)(epoch + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_tile = cnt;
-        s_tag = epoch;
-    }
+    if (threadIdx.x == 0) s_tile = compact_draw(ticket, ntiles, &s_tag);
     __syncthreads();
-    compact_tile<B, I>(x, y, count, n, t, s_tile, gridDim.x, status, s_tag, err, vec, L);
+    uint32_t tile = s_tile;
+    const uint32_t tag = s_tag;
+    while (tile < ntiles) {
+        compact_tile<B, I>(x, y, count, n, t, tile, ntiles, status, tag, err, vec, L, NoHook());
+        // The next tile is drawn only once this one is stored.  Drawn
+        // earlier (after the look-back, with or without its loads issued
+        // during this tile's copy-out) it starts its own stage late and
+        // holds up its successors' look-back: measured slower.
+        if (threadIdx.x == 0) {
+            uint32_t unused;
+            s_next = compact_draw(ticket, ntiles, &unused);
+        }
+        __syncthreads();  // s_next is written; the LDS stage is free again
+        tile = s_next;
+    }
 }
 
 size_t ws_compact_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return COMPACT_WS_HEADER + 8ull * grid.x; }
 
+template <int B, int I>
+static void launch_bi(uint32_t G, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t* cnt,
+                      uint32_t n, int32_t t, uint32_t* ws, uint32_t* err, bool vec, int num_cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, compact_i32_kernel<B, I>, B, dyn) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const uint32_t P = (uint32_t)std::min<uint64_t>(G, (uint64_t)per_cu * (uint64_t)num_cus);
+    hipLaunchKernelGGL((compact_i32_kernel<B, I>), dim3(P), dim3(B), dyn, s, x, y, cnt, n, t, G, ws, err, vec);
+}
+
 template <int B>
-static void launch_b(uint32_t I, dim3 g, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t* cnt,
-                     uint32_t n, int32_t t, uint32_t* ws, uint32_t* err, bool vec) {
-    dim3 b(B);
+static void launch_b(uint32_t I, uint32_t G, size_t dyn, hipStream_t s, const int32_t* x, int32_t* y, uint32_t* cnt,
+                     uint32_t n, int32_t t, uint32_t* ws, uint32_t* err, bool vec, int num_cus) {
     switch (I) {
-    case 1: hipLaunchKernelGGL((compact_i32_kernel<B, 1>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
-    case 2: hipLaunchKernelGGL((compact_i32_kernel<B, 2>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
-    case 4: hipLaunchKernelGGL((compact_i32_kernel<B, 4>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
-    case 8: hipLaunchKernelGGL((compact_i32_kernel<B, 8>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
-    case 16: hipLaunchKernelGGL((compact_i32_kernel<B, 16>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
-    case 32: hipLaunchKernelGGL((compact_i32_kernel<B, 32>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec); break;
+    case 1: launch_bi<B, 1>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
+    case 2: launch_bi<B, 2>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
+    case 4: launch_bi<B, 4>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
+    case 8: launch_bi<B, 8>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
+    case 16: launch_bi<B, 16>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
+    case 32: launch_bi<B, 32>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus); break;
     case 64:
-        if constexpr (B <= 512) hipLaunchKernelGGL((compact_i32_kernel<B, 64>), g, b, dyn, s, x, y, cnt, n, t, ws, err, vec);
+        if constexpr (B <= 512) launch_bi<B, 64>(G, dyn, s, x, y, cnt, n, t, ws, err, vec, num_cus);
         break;
     }
 }
@@ -66,14 +97,15 @@ int launch_compact_i32(const LaunchCtx& c) {
     const uint32_t I = next_pow2(per ? (uint32_t)per : 1u);
     if (I > 64 || (I == 64 && B > 512)) return SPMD_ERR_INVALID_DIM;
     const bool vec = aligned(x, 16);
-    dim3 g(c.grid.x);
+    const uint32_t G = c.grid.x;
     uint32_t* err = c.dev->err_word;
+    const int cus = c.dev->num_cus;
     switch (B) {
-    case 64: launch_b<64>(I, g, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec); break;
-    case 128: launch_b<128>(I, g, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec); break;
-    case 256: launch_b<256>(I, g, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec); break;
-    case 512: launch_b<512>(I, g, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec); break;
-    case 1024: launch_b<1024>(I, g, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec); break;
+    case 64: launch_b<64>(I, G, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec, cus); break;
+    case 128: launch_b<128>(I, G, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec, cus); break;
+    case 256: launch_b<256>(I, G, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec, cus); break;
+    case 512: launch_b<512>(I, G, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec, cus); break;
+    case 1024: launch_b<1024>(I, G, c.dyn_shmem, c.stream, x, y, cnt, n, t, ws, err, vec, cus); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
