@@ -79,8 +79,10 @@ enum {
      *       void* workspace (spmd_workspace_size bytes = 8320 + 8G, 16-byte
      *       aligned)
      * grid (G,1,1), block (B,1,1) with B a power of two in [64, 1024].
-     * Block b owns x[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G));
-     * partials[b] = sum of its elements, *out = sum of all n elements. */
+     * Block b owns x[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G))
+     * (SPMD_ERR_INVALID_DIM when S does not fit 32 bits: G = 1 and
+     * n > 2^32 - 4); partials[b] = sum of its elements, *out = sum of all n
+     * elements. */
     SPMD_REDUCE_I32 = 1,
 
     /* Inclusive prefix sum: y[i] = x[0] + ... + x[i] (mod 2^32), single
@@ -97,7 +99,9 @@ enum {
      * overwritten: the library clears it in stream order before counting.
      * args: const uint32_t* keys, uint32_t* hist, uint32_t n
      * grid (G,1,1), block (B,1,1), B a power of two in [64, 1024].  Block b
-     * counts keys[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G)). */
+     * counts keys[b*S, min((b+1)*S, n)), S = 4*ceil(n / (4G))
+     * (SPMD_ERR_INVALID_DIM when S does not fit 32 bits: G = 1 and
+     * n > 2^32 - 4). */
     SPMD_HIST256_U32 = 3,
 
     /* One sweep of the 5-point Laplace-Jacobi stencil on an ny x nx

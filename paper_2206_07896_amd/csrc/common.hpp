@@ -50,8 +50,10 @@ inline uint32_t next_pow2(uint32_t v) {
 inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // Segment of a block in the reduce and histogram classes: S = 4*ceil(n/(4G)).
-inline uint32_t segment_len(uint32_t n, uint32_t grid) {
-    return (uint32_t)(4ull * ((n + 4ull * grid - 1) / (4ull * grid)));
+// Elements per block, a multiple of 4: 4 * ceil(n / (4 * grid)).  It fits
+// 32 bits unless grid is 1 and n > 2^32 - 4; the launchers reject that.
+inline uint64_t segment_len(uint32_t n, uint32_t grid) {
+    return 4ull * ((n + 4ull * grid - 1) / (4ull * grid));
 }
 
 int hip_fail(hipError_t e);  // records the HIP error text, returns SPMD_ERR_HIP

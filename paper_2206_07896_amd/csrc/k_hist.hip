@@ -25,7 +25,9 @@ int launch_hist256_u32(const LaunchCtx& c) {
     auto n = arg<uint32_t>(c.args, 2);
     if ((!keys && n) || !hist) return SPMD_ERR_ARGS;
     const uint32_t G = c.grid.x;
-    const uint32_t seg = segment_len(n, G);
+    const uint64_t seg64 = segment_len(n, G);
+    if (seg64 > 0xFFFFFFFFull) return SPMD_ERR_INVALID_DIM;
+    const uint32_t seg = (uint32_t)seg64;
     const bool vec = aligned(keys, 16);
     hipLaunchKernelGGL(hist_clear_kernel, dim3(1), dim3(256), 0, c.stream, hist);
     if (n) {

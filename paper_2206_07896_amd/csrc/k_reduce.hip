@@ -34,7 +34,9 @@ int launch_reduce_i32(const LaunchCtx& c) {
     if ((!x && n) || !partials || !out) return SPMD_ERR_ARGS;
     if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
     const uint32_t G = c.grid.x;
-    const uint32_t seg = segment_len(n, G);
+    const uint64_t seg64 = segment_len(n, G);
+    if (seg64 > 0xFFFFFFFFull) return SPMD_ERR_INVALID_DIM;
+    const uint32_t seg = (uint32_t)seg64;
     const bool vec = aligned(x, 16);
     uint32_t* err = c.dev->err_word;
     dim3 g(G), b(B);

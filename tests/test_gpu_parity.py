@@ -412,6 +412,46 @@ def test_scan_graph_replays(spmd):
         assert np.array_equal(host(e), want), rep
 
 
+def test_maximum_size_closed_forms(spmd):
+    """n = 2^32 - 1, the largest count a uint32 argument holds (16 GiB per
+    array): scan of ones is y[i] = i + 1 mod 2^32, the sum of ones is
+    2^32 - 1 (int32 -1), every key in one bin fills it with 2^32 - 1, and
+    compaction keeps everything.  Element offsets pass 2^31 and 2^32 - 1, so
+    any 32-bit index in a kernel would show.  Checked on the device at 2^20
+    random positions plus both ends and the 2^31 boundary."""
+    import torch
+
+    n = 2**32 - 1
+    say("maximum size", n)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    idx = torch.randint(0, n, (1 << 20,), device="cuda", generator=g, dtype=torch.int64)
+    idx = torch.cat([idx, torch.tensor([0, 1, 2**31 - 2, 2**31 - 1, 2**31, 2**31 + 1, n - 2, n - 1],
+                                       device="cuda")])
+    as_i32 = lambda v: (v & 0xFFFFFFFF).to(torch.int32)  # noqa: E731 -- wrap to the int32 bit pattern
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = spmd.ops.scan_i32(x, 1024, 32)
+    spmd.sync()
+    assert bool(torch.equal(y[idx], as_i32(idx + 1)))
+    del y
+    torch.cuda.empty_cache()
+    _, out = spmd.ops.reduce_i32(x, 4096, 256)
+    spmd.sync()
+    assert int(out.item()) == -1
+    yc, cnt = spmd.ops.compact_i32(x, 0, 1024, 32)
+    spmd.sync()
+    assert int(cnt.item()) == -1  # 2^32 - 1 as int32
+    assert bool(torch.equal(yc[idx], x[idx]))
+    del yc
+    torch.cuda.empty_cache()
+    x.fill_(5 + 256 * 7)
+    h = spmd.ops.hist256_u32(x, 256, 1024)
+    spmd.sync()
+    hh = host(h, np.uint32)
+    assert int(hh[5]) == n and int(hh.astype(np.int64).sum()) == n
+    del x
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------------------------------------
 # COMPACT_I32 (warp vote: ballot + popc)
 # --------------------------------------------------------------------------
