@@ -677,28 +677,35 @@ def mixed_queue(spmd, count, reps=10):
     log(f"mixed: one-by-one {t_each:.2f} ms (captured {t_each_graph:.2f} ms), heuristic graph {t_graph:.2f} ms")
     model = L.load_default()
     if model is not None:
-        choice, _, sd = model.choose(specs)
-        sched = [L.CANDIDATES[j] for j in choice]
-        bl = spmd.batch.Batch(data.items(), sched)
-        stl = bl.stats()
-        data.outputs.fill_(-1)
-        bl.graph_launch()
-        spmd.sync()
-        same = same and bool(torch.equal(ref, data.outputs))
-        t_l = measure(bl.graph_launch, reps, warmup=2)
-        spmd.sync()
-        bl.close()
-        res["learned"] = {"schedule": "cost model (ensemble argmin of predicted time), no fallback",
-                          "chunks": stl["chunks"], "kernel_launches": stl["persistent_launches"],
-                          "ms_graph": round(t_l, 3),
-                          "launches_per_s": round(count / (t_l * 1e-3), 1),
-                          "speedup_vs_one_by_one": round(t_each / t_l, 3),
-                          "speedup_vs_one_by_one_captured_graph": round(t_each_graph / t_l, 3),
-                          "speedup_vs_heuristic": round(t_graph / t_l, 3),
-                          "GB/s": round(gbytes / (t_l * 1e-3), 1),
-                          "frac_hbm": round(gbytes / (t_l * 1e-3) / HBM_PEAK_GBS, 4),
-                          "low_confidence_launches": int((sd > model.tau).sum())}
-        log(f"mixed: learned graph {t_l:.2f} ms")
+        # per launch: the least predicted time of each launch alone; batch-
+        # aware: the fewest chunks within SPMD_BATCH_SLACK of it (the choice
+        # spmd_launch_batch makes in SPMD_SCHED_LEARNED mode)
+        for key, slack, what in (("learned", None, "cost model, least predicted time per launch, no fallback"),
+                                 ("learned_batch", L.BATCH_SLACK,
+                                  f"cost model, batch-aware: fewest chunks within {L.BATCH_SLACK:.0%} of the least "
+                                  "predicted time, no fallback")):
+            choice, _, sd = model.choose(specs, slack=slack)
+            sched = [L.CANDIDATES[j] for j in choice]
+            bl = spmd.batch.Batch(data.items(), sched)
+            stl = bl.stats()
+            data.outputs.fill_(-1)
+            bl.graph_launch()
+            spmd.sync()
+            same = same and bool(torch.equal(ref, data.outputs))
+            t_l = measure(bl.graph_launch, reps, warmup=2)
+            spmd.sync()
+            bl.close()
+            res[key] = {"schedule": what,
+                        "chunks": stl["chunks"], "kernel_launches": stl["persistent_launches"],
+                        "ms_graph": round(t_l, 3),
+                        "launches_per_s": round(count / (t_l * 1e-3), 1),
+                        "speedup_vs_one_by_one": round(t_each / t_l, 3),
+                        "speedup_vs_one_by_one_captured_graph": round(t_each_graph / t_l, 3),
+                        "speedup_vs_heuristic": round(t_graph / t_l, 3),
+                        "GB/s": round(gbytes / (t_l * 1e-3), 1),
+                        "frac_hbm": round(gbytes / (t_l * 1e-3) / HBM_PEAK_GBS, 4),
+                        "low_confidence_launches": int((sd > model.tau).sum())}
+            log(f"mixed: {key} graph {t_l:.2f} ms")
     res["outputs_identical"] = same
     del ref, data
     torch.cuda.empty_cache()

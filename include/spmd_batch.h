@@ -154,12 +154,25 @@ enum {
      * elements per thread from grid x block, and the paper's average
      * coarse-grained fetching, ceil(blocks / pool) per fetch (Section IV-A) */
     SPMD_SCHED_AS_LAUNCHED = 0,
-    /* the schedule of least predicted time under the loaded cost model
-     * (spmd_model_load); launches whose ensemble spread exceeds the model's
-     * threshold are tuned exhaustively instead (spmd_tune_time over every
-     * candidate), and that choice is cached by (class, sizes, blockDim) */
+    /* under the loaded cost model (spmd_model_load), batch-aware: among
+     * the schedules predicted within SPMD_BATCH_SLACK of the least, the one
+     * with the fewest chunks (spmd_mlp_choose_batch); launches whose
+     * ensemble spread exceeds the model's threshold are tuned exhaustively
+     * instead (spmd_tune_time over every candidate, fastest alone), and
+     * that choice is cached by (class, sizes, blockDim) */
     SPMD_SCHED_LEARNED = 1
 };
+
+/* Slack of the batch-aware learned choice: 20% over the least predicted
+ * time buys fewer chunks for the shared cursors (measured on the 10 000-
+ * launch mixed queue: 6.9 ms against 8.3 ms for the least predicted time
+ * per launch). */
+#define SPMD_BATCH_SLACK 0.2f
+
+/* Chunk counts of n launches under every candidate schedule (the order of
+ * spmd_sched_candidates): out[n x candidates], 0xFFFFFFFF where the
+ * candidate is invalid for the launch.  Host only. */
+int spmd_sched_chunks(const spmd_batch_item* items, int n, uint32_t* out);
 
 /* Workspace bytes that spmd_launch_batch needs for these launches under
  * any schedule (0 if a launch is invalid for batching). */

@@ -67,6 +67,20 @@ int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, c
                     const float* cands, uint32_t c, const uint8_t* valid, uint32_t* best, float* best_pred,
                     float* best_sd, void* stream);
 
+/* Batch-aware choice.  In a batch every launch's chunks are fetched from
+ * one shared cursor per queue by one atomic each, so the number of chunks
+ * is a cost of the batch that a launch timed alone does not show (fetching
+ * is atomic and costs, Section IV-A).  chunks[m x c] holds the chunk count
+ * of launch i under candidate j (spmd_sched_chunks).  Among the candidates
+ * whose mean prediction is within ln(1 + slack) of the least, the chosen
+ * one has the fewest chunks (then the smaller mean, then the lower index);
+ * slack 0 keeps only the candidates that tie with the least.  Outputs as
+ * spmd_mlp_choose (best_pred and best_sd at the chosen candidate).
+ * SPMD_ERR_ARGS for a null chunks or a negative or non-finite slack. */
+int spmd_mlp_choose_batch(const float* params, uint32_t k_models, const float* norm, const float* feats,
+                          uint32_t m, const float* cands, uint32_t c, const uint8_t* valid, const uint32_t* chunks,
+                          float slack, uint32_t* best, float* best_pred, float* best_sd, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,3 +114,31 @@ def ensemble_choose(params_list, feats, cands, valid, mu=None, inv_sd=None):
             if valid[i][j] and (best[i] < 0 or mean[j] < mean_at[i]):
                 best[i], mean_at[i], sd_at[i] = j, mean[j], sd[j]
     return best, mean_at, sd_at
+
+
+def ensemble_choose_batch(params_list, feats, cands, valid, chunks, slack, mu=None, inv_sd=None):
+    """Batch-aware choice (not in the paper; the library's rule for a batch,
+    where every chunk is one fetch from a shared cursor): per launch, the
+    valid candidates whose mean prediction is at most the least mean plus
+    ln(1 + slack); among them the fewest chunks, then the smaller mean, then
+    the lower index.  Returns (index, mean there, sd there); -1 when no
+    candidate is valid."""
+    feats = np.asarray(feats, dtype=np.float64)
+    cands = np.asarray(cands, dtype=np.float64)
+    m, c = feats.shape[0], cands.shape[0]
+    best = np.full(m, -1, dtype=np.int64)
+    mean_at = np.full(m, np.inf)
+    sd_at = np.zeros(m)
+    for i in range(m):
+        X = np.concatenate([np.repeat(feats[i:i + 1], c, axis=0), cands], axis=1)
+        preds = np.stack([forward(p, X, mu, inv_sd)[0] for p in params_list])
+        mean = preds.mean(axis=0)
+        sd = preds.std(axis=0)
+        ok = [j for j in range(c) if valid[i][j]]
+        if not ok:
+            continue
+        least = min(mean[j] for j in ok)
+        near = [j for j in ok if mean[j] <= least + np.log1p(slack)]
+        j = min(near, key=lambda q: (int(chunks[i][q]), mean[q], q))
+        best[i], mean_at[i], sd_at[i] = j, mean[j], sd[j]
+    return best, mean_at, sd_at

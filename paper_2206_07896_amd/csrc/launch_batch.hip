@@ -127,14 +127,15 @@ size_t batch_bound(const std::vector<spmd_batch_item>& items) {
 }
 
 struct InferLayout {
-    size_t cands, feats, valid, best, pred, sd, total;
+    size_t cands, feats, valid, chunks, best, pred, sd, total;
 };
 InferLayout infer_layout(size_t n) {
     InferLayout L;
     L.cands = 0;
     L.feats = align256(L.cands + 4 * SPMD_MLP_NSCHED * NCANDS);
     L.valid = align256(L.feats + 4 * SPMD_MLP_NFEAT * n);
-    L.best = align256(L.valid + NCANDS * n);
+    L.chunks = align256(L.valid + NCANDS * n);
+    L.best = align256(L.chunks + 4 * NCANDS * n);
     L.pred = align256(L.best + 4 * n);
     L.sd = align256(L.pred + 4 * n);
     L.total = align256(L.sd + 4 * n);
@@ -147,9 +148,29 @@ int current_device(int* d) {
     return (*d >= 0 && *d < MAX_DEVICES) ? SPMD_OK : SPMD_ERR_HIP;
 }
 
+// Chunks of one launch under candidate j in the block queue: its logical
+// blocks, fetched bpf at a time (SCAN one tile at a time); 0xFFFFFFFF where
+// the candidate is invalid for the launch.
+uint32_t candidate_chunks(const spmd_batch_item& it, uint32_t j) {
+    const spmd_schedule c = candidate(j);
+    if (!candidate_valid(it.kernel_id, c)) return 0xFFFFFFFFu;
+    const uint64_t nb = spmd_batch_item_blocks(&it, &c);
+    if (nb == 0) return 0xFFFFFFFFu;
+    const uint64_t bpf = it.kernel_id == SPMD_SCAN_I32 ? 1u : c.bpf;
+    const uint64_t ch = (nb + bpf - 1) / bpf;
+    return ch < 0xFFFFFFFFull ? (uint32_t)ch : 0xFFFFFFFEu;
+}
+
 }  // namespace
 
 extern "C" {
+
+int spmd_sched_chunks(const spmd_batch_item* items, int n, uint32_t* out) {
+    if (n < 0 || (n && (!items || !out))) return SPMD_ERR_ARGS;
+    for (int i = 0; i < n; ++i)
+        for (uint32_t j = 0; j < NCANDS; ++j) out[(size_t)NCANDS * i + j] = candidate_chunks(items[i], j);
+    return SPMD_OK;
+}
 
 uint32_t spmd_sched_candidates(spmd_schedule* out, uint32_t cap) {
     for (uint32_t j = 0; out && j < cap && j < NCANDS; ++j) out[j] = candidate(j);
@@ -256,6 +277,7 @@ int spmd_launch_batch(const spmd_launch_desc* descs, int n, int mode, void* work
         if (!m.k) return SPMD_ERR_ARGS;
         std::vector<float> cands(SPMD_MLP_NSCHED * NCANDS), feats((size_t)SPMD_MLP_NFEAT * n);
         std::vector<uint8_t> valid((size_t)NCANDS * n);
+        std::vector<uint32_t> chunks((size_t)NCANDS * n);
         for (uint32_t j = 0; j < NCANDS; ++j) {
             const spmd_schedule c = candidate(j);
             cands[3 * j + 0] = (float)log2((double)c.block);
@@ -264,18 +286,23 @@ int spmd_launch_batch(const spmd_launch_desc* descs, int n, int mode, void* work
         }
         for (int i = 0; i < n; ++i) {
             if ((rc = spmd_sched_features(&items[i], &feats[(size_t)SPMD_MLP_NFEAT * i]))) return rc;
-            for (uint32_t j = 0; j < NCANDS; ++j)
+            for (uint32_t j = 0; j < NCANDS; ++j) {
                 valid[(size_t)NCANDS * i + j] = candidate_valid(items[i].kernel_id, candidate(j)) ? 1 : 0;
+                chunks[(size_t)NCANDS * i + j] = candidate_chunks(items[i], j);
+            }
         }
         uint8_t* ws = static_cast<uint8_t*>(workspace);
         e = hipMemcpyAsync(ws + IL.cands, cands.data(), 4 * cands.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(ws + IL.feats, feats.data(), 4 * feats.size(), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(ws + IL.valid, valid.data(), valid.size(), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws + IL.chunks, chunks.data(), 4 * chunks.size(), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e);
-        rc = spmd_mlp_choose(m.params, m.k, m.norm, reinterpret_cast<const float*>(ws + IL.feats), (uint32_t)n,
-                             reinterpret_cast<const float*>(ws + IL.cands), NCANDS, ws + IL.valid,
-                             reinterpret_cast<uint32_t*>(ws + IL.best), reinterpret_cast<float*>(ws + IL.pred),
-                             reinterpret_cast<float*>(ws + IL.sd), stream);
+        rc = spmd_mlp_choose_batch(m.params, m.k, m.norm, reinterpret_cast<const float*>(ws + IL.feats), (uint32_t)n,
+                                   reinterpret_cast<const float*>(ws + IL.cands), NCANDS, ws + IL.valid,
+                                   reinterpret_cast<const uint32_t*>(ws + IL.chunks), SPMD_BATCH_SLACK,
+                                   reinterpret_cast<uint32_t*>(ws + IL.best), reinterpret_cast<float*>(ws + IL.pred),
+                                   reinterpret_cast<float*>(ws + IL.sd), stream);
         if (rc) return rc;
         std::vector<uint32_t> best(n);
         std::vector<float> sd(n);

@@ -166,13 +166,14 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ p, co
 __global__ __launch_bounds__(SPMD_MLP_MAX_CANDS) void mlp_choose_kernel(
     const float* __restrict__ params, uint32_t k_models, const float* __restrict__ norm,
     const float* __restrict__ feats, uint32_t m, const float* __restrict__ cands, uint32_t c,
-    const uint8_t* __restrict__ valid, uint32_t* __restrict__ best, float* __restrict__ best_pred,
-    float* __restrict__ best_sd) {
+    const uint8_t* __restrict__ valid, const uint32_t* __restrict__ chunks, float log_slack,
+    uint32_t* __restrict__ best, float* __restrict__ best_pred, float* __restrict__ best_sd) {
     extern __shared__ float P[];  // k_models * NP
     __shared__ float nm[2 * DIN];
     __shared__ float red_v[SPMD_MLP_MAX_CANDS];
     __shared__ uint32_t red_i[SPMD_MLP_MAX_CANDS];
     __shared__ float red_s[SPMD_MLP_MAX_CANDS];
+    __shared__ uint32_t red_c[SPMD_MLP_MAX_CANDS];
     for (uint32_t q = threadIdx.x; q < k_models * NP; q += blockDim.x) P[q] = params[q];
     if (threadIdx.x < 2 * DIN) nm[threadIdx.x] = norm[threadIdx.x];
     __syncthreads();
@@ -221,6 +222,33 @@ __global__ __launch_bounds__(SPMD_MLP_MAX_CANDS) void mlp_choose_kernel(
             }
             __syncthreads();
         }
+        if (chunks) {
+            // Batch-aware second pass: among the candidates whose mean is
+            // within log_slack of the least, the fewest chunks wins (then
+            // the smaller mean, then the lower index).
+            const float thr = red_v[0] + log_slack;
+            __syncthreads();  // every thread has read red_v[0]
+            const bool near = ok && mean <= thr;
+            red_c[j] = near ? chunks[(uint64_t)li * c + j] : 0xFFFFFFFFu;
+            red_v[j] = near ? mean : INFINITY;
+            red_i[j] = near ? j : 0xFFFFFFFFu;
+            red_s[j] = sd;
+            __syncthreads();
+            for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+                if (j < w) {
+                    const uint32_t ca = red_c[j], cb = red_c[j + w];
+                    const float a = red_v[j], b = red_v[j + w];
+                    const uint32_t ia = red_i[j], ib = red_i[j + w];
+                    if (cb < ca || (cb == ca && (b < a || (b == a && ib < ia)))) {
+                        red_c[j] = cb;
+                        red_v[j] = b;
+                        red_i[j] = ib;
+                        red_s[j] = red_s[j + w];
+                    }
+                }
+                __syncthreads();
+            }
+        }
         if (j == 0) {
             best[li] = red_i[0];
             best_pred[li] = red_v[0];
@@ -233,6 +261,12 @@ __global__ __launch_bounds__(SPMD_MLP_MAX_CANDS) void mlp_choose_kernel(
 }  // namespace spmd
 
 using namespace spmd;
+
+namespace {
+int choose_impl(const float* params, uint32_t k_models, const float* norm, const float* feats, uint32_t m,
+                const float* cands, uint32_t c, const uint8_t* valid, const uint32_t* chunks, float log_slack,
+                uint32_t* best, float* best_pred, float* best_sd, void* stream);
+}  // namespace
 
 extern "C" {
 
@@ -278,9 +312,28 @@ int spmd_mlp_adam(float* params, const float* grad, float* m, float* v, uint32_t
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }
 
+int spmd_mlp_choose_batch(const float* params, uint32_t k_models, const float* norm, const float* feats,
+                          uint32_t m, const float* cands, uint32_t c, const uint8_t* valid, const uint32_t* chunks,
+                          float slack, uint32_t* best, float* best_pred, float* best_sd, void* stream) {
+    if (!chunks || !(slack >= 0.0f) || !(slack < 1e30f)) return SPMD_ERR_ARGS;
+    return choose_impl(params, k_models, norm, feats, m, cands, c, valid, chunks, log1pf(slack), best, best_pred,
+                       best_sd, stream);
+}
+
 int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, const float* feats, uint32_t m,
                     const float* cands, uint32_t c, const uint8_t* valid, uint32_t* best, float* best_pred,
                     float* best_sd, void* stream) {
+    return choose_impl(params, k_models, norm, feats, m, cands, c, valid, nullptr, 0.0f, best, best_pred, best_sd,
+                       stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int choose_impl(const float* params, uint32_t k_models, const float* norm, const float* feats, uint32_t m,
+                const float* cands, uint32_t c, const uint8_t* valid, const uint32_t* chunks, float log_slack,
+                uint32_t* best, float* best_pred, float* best_sd, void* stream) {
     if (!params || !norm || k_models == 0 || k_models > SPMD_MLP_MAX_MODELS) return SPMD_ERR_ARGS;
     if (c == 0 || c > SPMD_MLP_MAX_CANDS || !cands) return SPMD_ERR_ARGS;
     if (m && (!feats || !valid || !best || !best_pred || !best_sd)) return SPMD_ERR_ARGS;
@@ -294,9 +347,10 @@ int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, c
     const uint32_t grid = m < 1024 ? m : 1024;
     clear_stale_error();
     hipLaunchKernelGGL(mlp_choose_kernel, dim3(grid), dim3(SPMD_MLP_MAX_CANDS), shm, static_cast<hipStream_t>(stream),
-                       params, k_models, norm, feats, m, cands, c, valid, best, best_pred, best_sd);
+                       params, k_models, norm, feats, m, cands, c, valid, chunks, log_slack, best, best_pred,
+                       best_sd);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }
 
-}  // extern "C"
+}  // namespace

@@ -49,6 +49,12 @@ _lib.spmd_mlp_backward.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, _P, _P, _P, 
 _lib.spmd_mlp_adam.argtypes = [_P, _P, _P, _P, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, _P]
 _lib.spmd_mlp_choose.argtypes = [_P, ctypes.c_uint32, _P, _P, ctypes.c_uint32, _P, ctypes.c_uint32, _P, _P, _P, _P, _P]
+_lib.spmd_mlp_choose_batch.argtypes = [_P, ctypes.c_uint32, _P, _P, ctypes.c_uint32, _P, ctypes.c_uint32, _P, _P,
+                                       ctypes.c_float, _P, _P, _P, _P]
+_lib.spmd_mlp_choose_batch.restype = ctypes.c_int
+_lib.spmd_sched_chunks.argtypes = [ctypes.POINTER(B.BatchItem), ctypes.c_int, _P]
+_lib.spmd_sched_chunks.restype = ctypes.c_int
+BATCH_SLACK = 0.2  # SPMD_BATCH_SLACK
 for _f in ("spmd_mlp_forward", "spmd_mlp_backward", "spmd_mlp_adam", "spmd_mlp_choose"):
     getattr(_lib, _f).restype = ctypes.c_int
 _lib.spmd_tune_workspace_size.argtypes = [ctypes.POINTER(B.BatchItem), ctypes.POINTER(B.Schedule), ctypes.c_int]
@@ -190,9 +196,11 @@ class CostModel:
                                      y.data_ptr(), None, None, _stream_handle(None)), "spmd_mlp_forward")
         return y.cpu().numpy()
 
-    def choose(self, specs):
+    def choose(self, specs, slack=None):
         """(candidate index, predicted log-us, ensemble sd) per spec, by the
-        inference kernel."""
+        inference kernel: the least predicted time per launch, or with
+        `slack` the batch-aware choice (spmd_mlp_choose_batch: fewest chunks
+        within ln(1 + slack) of the least)."""
         p, nm = self.device_tensors()
         m = len(specs)
         feats = torch.from_numpy(np.stack([launch_features(s) for s in specs])).cuda()
@@ -201,10 +209,29 @@ class CostModel:
         best = torch.empty(m, dtype=torch.int32, device="cuda")
         pred = torch.empty(m, dtype=torch.float32, device="cuda")
         sd = torch.empty(m, dtype=torch.float32, device="cuda")
-        _check(_lib.spmd_mlp_choose(p.data_ptr(), self.k, nm.data_ptr(), feats.data_ptr(), m, cands.data_ptr(),
-                                    len(CANDIDATES), valid.data_ptr(), best.data_ptr(), pred.data_ptr(),
-                                    sd.data_ptr(), _stream_handle(None)), "spmd_mlp_choose")
+        if slack is None:
+            _check(_lib.spmd_mlp_choose(p.data_ptr(), self.k, nm.data_ptr(), feats.data_ptr(), m, cands.data_ptr(),
+                                        len(CANDIDATES), valid.data_ptr(), best.data_ptr(), pred.data_ptr(),
+                                        sd.data_ptr(), _stream_handle(None)), "spmd_mlp_choose")
+        else:
+            ch = torch.from_numpy(sched_chunks(specs).view(np.int32)).cuda()
+            _check(_lib.spmd_mlp_choose_batch(p.data_ptr(), self.k, nm.data_ptr(), feats.data_ptr(), m,
+                                              cands.data_ptr(), len(CANDIDATES), valid.data_ptr(), ch.data_ptr(),
+                                              float(slack), best.data_ptr(), pred.data_ptr(), sd.data_ptr(),
+                                              _stream_handle(None)), "spmd_mlp_choose_batch")
         return best.cpu().numpy().astype(np.int64), pred.cpu().numpy(), sd.cpu().numpy()
+
+
+def sched_chunks(specs) -> np.ndarray:
+    """Chunk counts [len(specs) x candidates] (spmd_sched_chunks); 2^32 - 1
+    where a candidate is invalid for the launch."""
+    m = len(specs)
+    arr = (B.BatchItem * max(m, 1))()
+    for i, s in enumerate(specs):
+        arr[i] = B.BatchItem(int(s["kid"]), int(s["nx"]), int(s["ny"]), int(s["block_dim"]), None, None)
+    out = np.zeros((m, len(CANDIDATES)), np.uint32)
+    _check(_lib.spmd_sched_chunks(arr, m, out.ctypes.data), "spmd_sched_chunks")
+    return out
 
 
 def training_rows(specs, T):

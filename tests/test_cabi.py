@@ -297,3 +297,25 @@ def test_batch_dependencies_validated_on_host(spmd):
     assert size([None, 0, 1]) > 0                      # three levels
     assert size([0, None, None]) == 0                  # itself
     assert size([None, 2, None]) == 0                  # a later instance
+
+
+def test_sched_chunks_closed_forms(spmd):
+    """Chunk counts per candidate: ceil(blocks / bpf), SCAN one tile per
+    chunk, 2^32 - 1 where the candidate is invalid for the class."""
+    from paper_2206_07896_amd import learned as L
+
+    specs = [{"kid": spmd.REDUCE_I32, "nx": 100000, "ny": 1, "block_dim": 256},
+             {"kid": spmd.SCAN_I32, "nx": 100000, "ny": 1, "block_dim": 256},
+             {"kid": spmd.JACOBI5_F32, "nx": 300, "ny": 200, "block_dim": 128}]
+    ch = L.sched_chunks(specs)
+    C = L.CANDIDATES
+    assert ch.shape == (3, len(C))
+    for j, (blk, it, bpf) in enumerate(C):
+        nb = -(-100000 // (blk * it))
+        assert ch[0, j] == -(-nb // bpf), (blk, it, bpf)
+        assert ch[1, j] == nb                                   # scan: one tile per chunk
+        if it > 8:
+            assert ch[2, j] == 0xFFFFFFFF                       # Jacobi takes at most 8 cells per thread
+        else:
+            nbj = -(-300 // 64) * -(-200 // ((blk // 64) * it))  # 64-column blocks of blk/64 rows x it cells
+            assert ch[2, j] == -(-nbj // bpf)

@@ -271,3 +271,64 @@ def test_tune_time_measures_and_computes(L):
     assert total == int(x.astype(np.int64).sum())  # closed form, |sum| < 2^31
     with pytest.raises(ValueError):
         tuner.time((spmd.REDUCE_I32, n, 1, 256, tin, tout), [(256, 3, 1)])
+
+
+@pytest.mark.parametrize("slack", [0.0, 0.05, 0.2, 1.0])
+def test_choose_batch_matches_oracle(L, slack):
+    """spmd_mlp_choose_batch against the FP64 oracle's batch-aware rule:
+    fewest chunks among the candidates within ln(1 + slack) of the least
+    mean.  Launches with a candidate within fp32 rounding of the threshold
+    are checked for validity only."""
+    import torch
+
+    say("mlp choose batch", slack)
+    rng = np.random.default_rng(77)
+    m, c, k = 200, 120, 3
+    feats = (rng.standard_normal((m, 9)) * 2.0).astype(np.float32)
+    cands = (rng.standard_normal((c, 3)) * 2.0).astype(np.float32)
+    valid = rng.random((m, c)) < 0.8
+    valid[3, :] = False
+    chunks = rng.integers(1, 40, (m, c)).astype(np.uint32)
+    params = [omlp.init_params(60 + q).astype(np.float32) for q in range(k)]
+    mu = rng.standard_normal(12).astype(np.float32) * 0.1
+    inv_sd = (0.5 + rng.random(12)).astype(np.float32)
+    best = torch.empty(m, dtype=torch.int32, device="cuda")
+    pred = torch.empty(m, dtype=torch.float32, device="cuda")
+    sd = torch.empty(m, dtype=torch.float32, device="cuda")
+    dp, dn, df, dc = cuda(np.concatenate(params)), cuda(np.concatenate([mu, inv_sd])), cuda(feats), cuda(cands)
+    dv = cuda(valid.astype(np.uint8), np.uint8)
+    dch = cuda(chunks.view(np.int32), np.int32)
+    ok(L._lib.spmd_mlp_choose_batch(dp.data_ptr(), k, dn.data_ptr(), df.data_ptr(), m, dc.data_ptr(), c,
+                                    dv.data_ptr(), dch.data_ptr(), float(slack), best.data_ptr(), pred.data_ptr(),
+                                    sd.data_ptr(), None), "spmd_mlp_choose_batch")
+    got = best.cpu().numpy().view(np.uint32)
+    p64 = [q.astype(np.float64) for q in params]
+    ob, om, osd = omlp.ensemble_choose_batch(p64, feats, cands, valid, chunks, slack, mu.astype(np.float64),
+                                             inv_sd.astype(np.float64))
+    X = np.concatenate([np.repeat(feats, c, axis=0), np.tile(cands, (m, 1))], axis=1)
+    means = np.mean([omlp.forward(q, X, mu.astype(np.float64), inv_sd.astype(np.float64))[0] for q in p64],
+                    axis=0).reshape(m, c)
+    means = np.where(valid, means, np.inf)
+    scale = max(1.0, float(np.max(np.abs(means[np.isfinite(means)]))))
+    tol = 1e-4 * scale
+    assert got[3] == 0xFFFFFFFF and ob[3] == -1
+    strict = 0
+    for i in range(m):
+        if ob[i] < 0:
+            continue
+        j = int(got[i])
+        assert j < c and valid[i, j]
+        thr = np.min(means[i]) + np.log1p(slack)
+        assert means[i, j] <= thr + tol
+        inside = means[i] <= thr - tol
+        if inside.any():  # candidates surely within the slack: none has fewer chunks
+            assert chunks[i, j] <= chunks[i][inside].min()
+        boundary = np.abs(means[i] - thr) <= tol
+        if slack == 0:
+            boundary[np.argmin(means[i])] = False  # at slack 0 the least itself sits on the threshold
+        if not boundary.any():
+            ties = np.sort(means[i][(chunks[i] == chunks[i, j]) & (means[i] <= thr)])
+            if ties.size == 1 or ties[1] - ties[0] > tol:
+                assert j == ob[i], i
+                strict += 1
+    assert strict > m // 2

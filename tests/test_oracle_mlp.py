@@ -131,3 +131,61 @@ def test_ensemble_choose_mean_and_sd_of_two_models():
     best1, mean1, _ = mlp.ensemble_choose([p], feats, cands, np.ones((3, 4), bool))
     assert list(best) == list(best1)
     assert np.allclose(mean, mean1, rtol=0, atol=1e-12) and np.allclose(sd, 0.75, rtol=0, atol=1e-12)
+
+
+def _pass_through_model():
+    """A model whose prediction is the first schedule input (x[9]) for
+    x[9] >= 0: one ReLU path with unit weights, everything else zero."""
+    flat = np.zeros(mlp.NPARAM)
+    o = 0
+    for name, shape in mlp.SIZES:
+        k = int(np.prod(shape))
+        if name == "W1":
+            w = np.zeros(shape)
+            w[9, 0] = 1.0
+            flat[o:o + k] = w.ravel()
+        elif name == "W2":
+            w = np.zeros(shape)
+            w[0, 0] = 1.0
+            flat[o:o + k] = w.ravel()
+        elif name == "w3":
+            w = np.zeros(shape)
+            w[0] = 1.0
+            flat[o:o + k] = w
+        o += k
+    return flat
+
+
+def test_ensemble_choose_batch_hand_case():
+    # predictions 0, 0.1, 0.3, 0.05 (the first schedule input); chunks 10, 5, 1, 7
+    p = _pass_through_model()
+    feats = np.zeros((1, 9))
+    cands = np.array([[0.0, 0, 0], [0.1, 0, 0], [0.3, 0, 0], [0.05, 0, 0]])
+    valid = np.ones((1, 4), bool)
+    chunks = np.array([[10, 5, 1, 7]])
+    mu, inv_sd = np.zeros(12), np.ones(12)
+    pick = lambda slack: int(mlp.ensemble_choose_batch([p], feats, cands, valid, chunks, slack, mu, inv_sd)[0][0])  # noqa: E731
+    assert pick(0.0) == 0                     # nothing within slack but the least itself
+    assert pick(np.expm1(0.15)) == 1          # 0, 0.1 and 0.05 are near: 5 chunks is fewest
+    assert pick(np.expm1(0.35)) == 2          # all near: the single chunk wins
+    assert pick(np.expm1(0.07)) == 3          # 0 and 0.05 near: 7 chunks beat 10
+    valid[0, 2] = False
+    assert pick(np.expm1(0.35)) == 1          # the invalid candidate is never chosen
+
+
+def test_ensemble_choose_batch_reduces_to_plain_choice_and_breaks_ties():
+    rng = np.random.default_rng(11)
+    params = [mlp.init_params(3), mlp.init_params(4)]
+    feats = rng.standard_normal((6, 9))
+    cands = rng.standard_normal((20, 3))
+    valid = rng.random((6, 20)) < 0.7
+    chunks = rng.integers(1, 50, (6, 20))
+    b0, m0, _ = mlp.ensemble_choose(params, feats, cands, valid)
+    b1, m1, _ = mlp.ensemble_choose_batch(params, feats, cands, valid, chunks, 0.0)
+    assert np.array_equal(b0, b1) and np.allclose(m0, m1)
+    # equal predictions everywhere (zero weights, one bias): fewest chunks, then lowest index
+    const = np.zeros(mlp.NPARAM)
+    const[-1] = 2.5
+    chunks = np.array([[4, 2, 2, 9]])
+    b, m, _ = mlp.ensemble_choose_batch([const], np.zeros((1, 9)), np.zeros((4, 3)), np.ones((1, 4), bool), chunks, 0.0)
+    assert int(b[0]) == 1 and m[0] == 2.5
