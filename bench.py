@@ -284,6 +284,7 @@ def calibration_copies():
 def extra_workloads(spmd, synth):
     """Per-kernel figures of the other workloads (not part of the step)."""
     res = copy_reference()
+    res.update(vendor_scan_reference(synth))
     res.update(reduce_workloads(spmd, synth))
     res.update(jacobi_workloads(spmd, synth))
     res.update(hist_contention_workloads(spmd, synth))
@@ -305,6 +306,23 @@ def copy_reference():
     res["reference: device copy 256 MiB (torch copy_)"] = {"us": round(ms * 1e3, 2),
                                                           "GB/s": round(8 * (1 << 26) / ms / 1e6, 1)}
     del src, dst
+    return res
+
+
+def vendor_scan_reference(synth):
+    """Reference only: the framework's own device scan (torch.cumsum, int32
+    in and out) on the step's
+    scan input, 2^26 int32 U[0,100]; 8 bytes per element."""
+    import torch
+
+    n = 1 << 26
+    x = to_dev(synth.uniform_int32(synth.SEED_SCAN, n, 0, 100))
+    y = torch.empty_like(x)
+    ms = measure(lambda: torch.cumsum(x, 0, dtype=torch.int32, out=y), 20)
+    res = {"reference: torch.cumsum int32 2^26": {"us": round(ms * 1e3, 2), "GB/s": round(8 * n / ms / 1e6, 1),
+                                                  "frac_hbm": round(8 * n / ms / 1e6 / HBM_PEAK_GBS, 4)}}
+    del x, y
+    torch.cuda.empty_cache()
     return res
 
 
@@ -568,6 +586,9 @@ def compact_workloads(spmd, synth):
         res[f"compact_i32 2^26 t=0 b{block} i{items}"] = {"us": round(ms * 1e3, 2), "kept": m,
                                                           "GB/s": round(byts / ms / 1e6, 1),
                                                           "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    # reference only: the framework's selection (torch.masked_select) on the same input, same bytes
+    ms = measure(lambda: torch.masked_select(xs[0], xs[0] > 0), 20)
+    res["reference: torch.masked_select 2^26 t=0"] = {"us": round(ms * 1e3, 2), "GB/s": round(byts / ms / 1e6, 1)}
     del xs, y
     torch.cuda.empty_cache()
     return res

@@ -449,6 +449,52 @@ def load_default():
         return CostModel.from_json(f.read())
 
 
+def contention_study(model=None, log2_sizes=(12, 14, 16, 18, 20, 22), reps=5, log=None):
+    """Does LDS-atomic contention move a histogram's best schedule?  For
+    each size, keys of bounded Zipf exponent 0 (uniform), 1.1 (the workload's),
+    2 and 3, and every key in one bin, are timed under every candidate
+    schedule.  Per row: the best time and schedule, the regret of the
+    schedule that is best at exponent 1.1 (what a model trained on the
+    workload would learn), and, with a model, the regret of its choice.
+    The launch features carry no key distribution, so these regrets bound
+    what a contention feature could recover (Section V-C: the grain size
+    depends on the kernel's atomics)."""
+    import synth
+
+    tuner = Autotuner(reps=reps)
+    dists = (("zipf0", 0.0), ("zipf1.1", 1.1), ("zipf2", 2.0), ("zipf3", 3.0), ("one bin", None))
+    hist = torch.zeros(256, dtype=torch.int32, device="cuda")
+    rows = []
+    for lg in log2_sizes:
+        n = 1 << lg
+        keys = torch.empty(n, dtype=torch.int32, device="cuda")
+        T = {}
+        for name, alpha in dists:
+            if alpha is None:
+                keys.fill_(7)
+            else:
+                B.synth_zipf_u32(keys, synth.SEED_HIST ^ lg, torch.from_numpy(synth.zipf_cdf(alpha, 256)).cuda())
+            item = (HIST256_U32, n, 1, 256, keys, hist)
+            # two full sweeps, the faster of each: at ~10 us a single stall skews one timing
+            T[name] = np.minimum(tuner.time(item, CANDIDATES), tuner.time(item, CANDIDATES))
+        spec = {"kid": HIST256_U32, "n": n, "nx": n, "ny": 1, "block_dim": 256}
+        chosen = int(model.choose([spec])[0][0]) if model is not None else None
+        ref = int(np.argmin(T["zipf1.1"]))
+        for name, _ in dists:
+            t = T[name]
+            j = int(np.argmin(t))
+            row = {"log2_n": lg, "keys": name, "best_us": round(float(t[j]) * 1e3, 2), "best": list(CANDIDATES[j]),
+                   "regret_of_zipf1.1_best": round(float(t[ref] / t[j] - 1.0), 4)}
+            if chosen is not None:
+                row["model"] = list(CANDIDATES[chosen])
+                row["regret_of_model"] = round(float(t[chosen] / t[j] - 1.0), 4)
+            rows.append(row)
+            if log is not None:
+                log(json.dumps(row))
+        del keys
+    return rows
+
+
 def main(argv=None):
     import argparse
     import sys
@@ -460,10 +506,21 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--out", default=MODEL_PATH)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--contention", action="store_true",
+                    help="only time histograms of skewed keys under every schedule (no training)")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if a.contention:
+        rows = contention_study(load_default(), log=log)
+        text = json.dumps(rows)
+        print(text, flush=True)
+        if a.report:
+            with open(a.report, "w") as f:
+                f.write(text + "\n")
+        return
 
     res, model = evaluate(a.train_count, a.heldout, a.models, a.steps, log=log)
     with open(a.out, "w") as f:

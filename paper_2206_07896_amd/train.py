@@ -2,6 +2,7 @@
 and write the model next to the package (``cost_model.json``).
 
     python -m paper_2206_07896_amd.train [--train-count 500] [--heldout 2000]
+    python -m paper_2206_07896_amd.train --contention   # skewed-key histogram schedules only
 """
 
 from .learned import main

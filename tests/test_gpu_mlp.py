@@ -273,6 +273,20 @@ def test_tune_time_measures_and_computes(L):
         tuner.time((spmd.REDUCE_I32, n, 1, 256, tin, tout), [(256, 3, 1)])
 
 
+def test_contention_study_rows(L):
+    """The skewed-key schedule study: one row per key distribution, the
+    regrets are ratios of timings of the same instance (>= 0), and the
+    exponent-1.1 row's own best has zero regret."""
+    say("contention study 2^12")
+    rows = L.contention_study(None, log2_sizes=(12,), reps=1)
+    assert [r["keys"] for r in rows] == ["zipf0", "zipf1.1", "zipf2", "zipf3", "one bin"]
+    cands = {tuple(c) for c in L.CANDIDATES}
+    for r in rows:
+        assert r["log2_n"] == 12 and r["best_us"] > 0 and tuple(r["best"]) in cands
+        assert r["regret_of_zipf1.1_best"] >= 0
+    assert rows[1]["regret_of_zipf1.1_best"] == 0
+
+
 @pytest.mark.parametrize("slack", [0.0, 0.05, 0.2, 1.0])
 def test_choose_batch_matches_oracle(L, slack):
     """spmd_mlp_choose_batch against the FP64 oracle's batch-aware rule:
