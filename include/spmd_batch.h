@@ -5,9 +5,14 @@
  * launches into a task queue, workers fetch blocks from it in chunks of
  * block_per_fetch blocks ("coarse-grained fetching", Section IV-A), and the
  * fetch itself is one atomic operation on the queue's cursor.  Here the
- * workers are resident workgroups, the cursor is a device counter advanced
+ * workers are resident workgroups, a cursor is a device counter advanced
  * with one relaxed device-scope atomic per fetch, and the queue is a table
- * of chunks (instance, first logical block) built on the host.  A batch is
+ * of chunks (instance, first logical block) built on the host.  A scan
+ * queue has one cursor, so its tiles start in order; any other queue cuts
+ * its chunks into up to 8 contiguous ranges with a cursor each (workgroup
+ * w serves range w mod 8, i.e. one XCD, and moves on to the other ranges
+ * once its own is drained), which spreads the fetch atomics over 8
+ * counters and keeps a range's data in one XCD's L2.  A batch is
  * prepared once (spmd_batch_create: descriptors and chunk tables uploaded,
  * optional hipGraph captured) and then run any number of times.
  *
@@ -164,9 +169,8 @@ enum {
 };
 
 /* Slack of the batch-aware learned choice: 20% over the least predicted
- * time buys fewer chunks for the shared cursors (measured on the 10 000-
- * launch mixed queue: 6.9 ms against 8.3 ms for the least predicted time
- * per launch). */
+ * time buys fewer chunks to fetch (measured on the 10 000-launch mixed
+ * queue: 6.8 ms against 7.8 ms for the least predicted time per launch). */
 #define SPMD_BATCH_SLACK 0.2f
 
 /* Chunk counts of n launches under every candidate schedule (the order of

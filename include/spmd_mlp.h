@@ -68,7 +68,7 @@ int spmd_mlp_choose(const float* params, uint32_t k_models, const float* norm, c
                     float* best_sd, void* stream);
 
 /* Batch-aware choice.  In a batch every launch's chunks are fetched from
- * one shared cursor per queue by one atomic each, so the number of chunks
+ * its queue's cursors by one atomic each, so the number of chunks
  * is a cost of the batch that a launch timed alone does not show (fetching
  * is atomic and costs, Section IV-A).  chunks[m x c] holds the chunk count
  * of launch i under candidate j (spmd_sched_chunks).  Among the candidates

@@ -2,7 +2,7 @@
 //
 // Queue layout (all in the caller's workspace):
 //   run area    cleared by the prologue kernel on every run:
-//                 one fetch cursor per segment, 64 B apart,
+//                 per segment 1 KiB of fetch cursors (8, 128 B apart),
 //                 then per-instance scratch (REDUCE: ticket on its own
 //                 line + one status word per block; SCAN: one status
 //                 word per tile), 256-byte aligned
@@ -21,11 +21,14 @@
 // chunks of a segment are numbered instance by instance, blocks ascending,
 // so a scan's tiles are fetched in order (its look-back waits only for
 // tiles fetched earlier).  A persistent workgroup takes a chunk with one
-// relaxed atomic add on its segment's cursor and requests the next chunk
-// as soon as it starts the current one, so the atomic's round trip
-// overlaps the block bodies.  It exits when the cursor passes the
-// segment's chunk count, so every workgroup ends after finitely many
-// fetches.
+// relaxed atomic add on a cursor and requests the next chunk as soon as it
+// starts the current one, so the atomic's round trip overlaps the block
+// bodies.  A SCAN segment has one cursor.  Every other segment cuts its
+// chunks into up to 8 contiguous ranges with a cursor each (ChunkRanges
+// below): a range's chunks run on one XCD and its draws do not queue
+// behind the other ranges'.  A workgroup exits once every cursor it draws
+// from has passed the end of its range, so every workgroup ends after
+// finitely many fetches.
 #include <string.h>
 
 #include <algorithm>
@@ -164,55 +167,127 @@ __device__ __forceinline__ void run_fused_chunk(const BatchDesc& d, uint32_t q, 
     }
 }
 
+// Chunk ranges of a segment whose chunks may run in any order (every class
+// but SCAN).  The chunks are cut into R = min(8, workers) contiguous ranges
+// with one cursor each, 128 bytes apart.  Worker w belongs to range w mod R:
+// the hardware deals a grid's workgroups to the 8 XCDs round-robin, so a
+// range runs on one XCD and its instances' lines -- a stencil's neighbouring
+// tiles above all -- meet in that XCD's L2, and each cursor takes 1/R of the
+// draws.  (Were the dealing different, only the locality would suffer.)
+// Range sizes follow the ranges' worker counts, so with as many chunks as
+// workers every chunk is some worker's static one.  Worker w's first chunk
+// is chunk w div R of its range, taken without a draw; range q's draws hand
+// out its chunks from lo(q) + workers(q) on, and a range with no chunk
+// beyond the static ones is closed from the start.  Once a range is
+// exhausted the worker reads the other open ranges' cursors (one round of
+// plain loads, in parallel: a cursor only grows, so a range seen exhausted
+// stays so), draws from the next range still open, and exits when none is.
+// The host computes the table (range_table below) once per segment; the
+// kernel copies it to LDS, where wave 0 reads it at chunk ends.
+struct RangeTable {
+    uint32_t lo[BATCH_CURSOR_RANGES + 1];   // first chunk of range q; lo[R] = the chunk count
+    uint32_t wlo[BATCH_CURSOR_RANGES + 1];  // workers of ranges 0 .. q-1
+    uint32_t nrange;                        // R
+    uint32_t closed;                        // ranges with no chunk to draw, one bit each
+};
+
+RangeTable range_table(uint32_t workers, uint32_t chunks) {
+    RangeTable t{};
+    const uint32_t R = workers < BATCH_CURSOR_RANGES ? workers : (uint32_t)BATCH_CURSOR_RANGES;
+    t.nrange = R;
+    for (uint32_t q = 0; q <= R; ++q) {
+        t.wlo[q] = R ? q * (workers / R) + (q < workers % R ? q : workers % R) : 0u;
+        t.lo[q] = workers ? (uint32_t)((uint64_t)chunks * t.wlo[q] / workers) : 0u;
+    }
+    for (uint32_t q = 0; q < R; ++q)
+        if (t.lo[q + 1] - t.lo[q] <= t.wlo[q + 1] - t.wlo[q]) t.closed |= 1u << q;
+    return t;
+}
+
+struct ChunkRanges {
+    static constexpr uint32_t CURSOR_WORDS = (uint32_t)BATCH_CURSOR_SLOT / 4;
+    const RangeTable& T;  // the LDS copy
+    uint32_t cur;
+    uint32_t done;  // ranges known exhausted, one bit each (wave 0's copy is the live one)
+    uint32_t* cursor;
+
+    __device__ ChunkRanges(const RangeTable& t, uint32_t* c)
+        : T(t), cur(blockIdx.x % t.nrange), done(t.closed), cursor(c) {}
+    __device__ uint32_t total() const { return T.lo[T.nrange]; }
+    // chunk of draw value v on range q, or total() if the range has none left
+    __device__ uint32_t chunk_of(uint32_t q, uint32_t v) const {
+        const uint64_t idx = (uint64_t)T.lo[q] + (T.wlo[q + 1] - T.wlo[q]) + v;
+        return idx < (uint64_t)T.lo[q + 1] ? (uint32_t)idx : total();
+    }
+    // this worker's static chunk, or total() if its range is too short
+    __device__ uint32_t first() const {
+        const uint32_t c = T.lo[cur] + blockIdx.x / T.nrange;
+        return c < T.lo[cur + 1] ? c : total();
+    }
+    // is there a range to draw from now (false: resolve() without a draw)
+    __device__ bool open() const { return !(done >> cur & 1u); }
+    // one draw on the current range (one lane)
+    __device__ uint32_t draw() const { return atomic_add_dev(cursor + CURSOR_WORDS * cur, 1u); }
+    // Wave 0, all 64 lanes: the chunk that lane 0's draw `raw` on the current
+    // range gives (when `drawn`), else one from a range still open, else
+    // total().  Lane q reads range q's cursor, one ballot marks the exhausted.
+    __device__ uint32_t resolve(uint32_t raw, bool drawn) {
+        const uint32_t R = T.nrange, all = (1u << R) - 1u, lane = lane64();
+        raw = __builtin_amdgcn_readfirstlane(raw);
+        for (;;) {
+            if (drawn) {
+                const uint32_t c = chunk_of(cur, raw);
+                if (c < total()) return c;
+                done |= 1u << cur;
+            }
+            if (done == all) return total();
+            const uint32_t ql = lane < R ? lane : 0u;  // lanes past R index range 0, unused
+            const bool probe = lane < R && !(done >> lane & 1u);
+            const uint32_t v = probe ? load_dev(cursor + CURSOR_WORDS * ql) : 0u;
+            done |= (uint32_t)__builtin_amdgcn_ballot_w64(probe && chunk_of(ql, v) >= total());
+            if (done == all) return total();
+            while (done >> cur & 1u) cur = cur + 1u < R ? cur + 1u : 0u;
+            raw = 0;
+            if (lane == 0) raw = draw();
+            raw = __builtin_amdgcn_readfirstlane(raw);
+            drawn = true;
+        }
+    }
+};
+
 template <int CLS, int B>
 __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __restrict__ descs,
                                                               const uint32_t* __restrict__ chunk_inst,
                                                               uint32_t total_chunks, uint32_t* cursor,
-                                                              uint32_t* err) {
+                                                              uint32_t* err, RangeTable ranges) {
     __shared__ BatchLdsOf<CLS, B> L;
     __shared__ uint32_t s_next;
+    __shared__ RangeTable s_ranges;
     const uint32_t t = threadIdx.x;
-    // Chunk numbers handed out by the cursor.  Every class but SCAN takes
-    // its first chunk statically (chunk blockIdx.x; the grid never exceeds
-    // the chunk count), which saves one serialized atomic per worker.  SCAN
-    // takes every chunk from the cursor, so a tile is only ever owned by a
-    // running worker and the tiles its look-back waits on are in progress
-    // even when other kernels hold some of the compute units.
-    constexpr bool STATIC_FIRST = CLS != SPMD_SCAN_I32;
-    const uint32_t base = STATIC_FIRST ? gridDim.x : 0u;
-    uint32_t c;
-    if constexpr (STATIC_FIRST) {
-        c = blockIdx.x;
-    } else {
+    if constexpr (CLS == SPMD_SCAN_I32) {
+        // One cursor, every chunk drawn from it: tiles start in order and a
+        // tile is only ever owned by a running worker, so the tiles a
+        // look-back waits on are in progress even when other kernels hold
+        // some of the compute units.  The next draw is made once the tile
+        // has published its inclusive prefix: drawn earlier, a reserved
+        // tile that has not started would hold up its successors' look-back
+        // while this worker is itself waiting in a look-back.
         if (t == 0) s_next = atomic_add_dev(cursor, 1u);
         __syncthreads();
-        c = __builtin_amdgcn_readfirstlane(s_next);
-    }
-    while (c < total_chunks) {
-        __syncthreads();  // every thread has read s_next
-        // The next fetch is issued early so its round trip overlaps this
-        // chunk -- except for SCAN, where a reserved tile that has not
-        // started would hold up its successors' look-back while this worker
-        // is itself waiting in a look-back: SCAN fetches once its tile has
-        // published its inclusive prefix.
-        uint32_t nxt = 0;
-        bool fetched = false;
-        if (CLS != SPMD_SCAN_I32 && t == 0) {
-            nxt = base + atomic_add_dev(cursor, 1u);
-            fetched = true;
-        }
-        const BatchDesc d = descs[chunk_inst[c]];
-        const uint32_t first = (c - d.chunk0) * d.bpf;
-        const uint32_t last = min(first + d.bpf, d.nblocks);
-        if (t == 0 && (first >= last || d.cls != (uint32_t)CLS)) atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
-        if (d.cls != (uint32_t)CLS) break;
-        if constexpr (CLS == SPMD_REDUCE_I32 || CLS == SPMD_HIST256_U32) {
-            run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
-            __syncthreads();
-        } else {
+        uint32_t c = __builtin_amdgcn_readfirstlane(s_next);
+        while (c < total_chunks) {
+            __syncthreads();  // every thread has read s_next
+            uint32_t nxt = 0;
+            bool fetched = false;
+            const BatchDesc d = descs[chunk_inst[c]];
+            const uint32_t first = (c - d.chunk0) * d.bpf;
+            const uint32_t last = min(first + d.bpf, d.nblocks);
+            if (t == 0 && (first >= last || d.cls != (uint32_t)CLS))
+                atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
+            if (d.cls != (uint32_t)CLS) break;
             auto fetch_once = [&]() {
                 if (!fetched) {
-                    nxt = base + atomic_add_dev(cursor, 1u);
+                    nxt = atomic_add_dev(cursor, 1u);
                     fetched = true;
                 }
             };
@@ -220,13 +295,52 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
                 run_logical_block<CLS, B>(d, b, L, err, fetch_once);
                 __syncthreads();  // the next logical block reuses the LDS
             }
+            if (t == 0) s_next = fetched ? nxt : atomic_add_dev(cursor, 1u);
+            __syncthreads();
+            c = __builtin_amdgcn_readfirstlane(s_next);
         }
-        if (t == 0) {
-            if (!fetched) nxt = base + atomic_add_dev(cursor, 1u);
-            s_next = nxt;
-        }
+    } else {
+        if (t == 0) s_ranges = ranges;
         __syncthreads();
-        c = __builtin_amdgcn_readfirstlane(s_next);
+        ChunkRanges q(s_ranges, cursor);
+        uint32_t c = __builtin_amdgcn_readfirstlane(q.first());  // block-uniform
+        if (c >= total_chunks) {
+            if (t < 64) {
+                const bool drawn = q.open();
+                const uint32_t r = q.resolve(drawn && t == 0 ? q.draw() : 0u, drawn);
+                if (t == 0) s_next = r;
+            }
+            __syncthreads();
+            c = __builtin_amdgcn_readfirstlane(s_next);
+        }
+        while (c < total_chunks) {
+            __syncthreads();  // every thread has read s_next
+            // the next draw is issued now; its round trip overlaps the chunk
+            const bool drawn = t < 64 && q.open();  // wave-uniform in wave 0
+            uint32_t raw = 0;
+            if (drawn && t == 0) raw = q.draw();
+            const BatchDesc d = descs[chunk_inst[c]];
+            const uint32_t first = (c - d.chunk0) * d.bpf;
+            const uint32_t last = min(first + d.bpf, d.nblocks);
+            if (t == 0 && (first >= last || d.cls != (uint32_t)CLS))
+                atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
+            if (d.cls != (uint32_t)CLS) break;
+            if constexpr (CLS == SPMD_REDUCE_I32 || CLS == SPMD_HIST256_U32) {
+                run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
+                __syncthreads();
+            } else {
+                for (uint32_t b = first; b < last; ++b) {
+                    run_logical_block<CLS, B>(d, b, L, err, NoHook());
+                    __syncthreads();  // the next logical block reuses the LDS
+                }
+            }
+            if (t < 64) {
+                const uint32_t r = q.resolve(raw, drawn);
+                if (t == 0) s_next = r;
+            }
+            __syncthreads();
+            c = __builtin_amdgcn_readfirstlane(s_next);
+        }
     }
 }
 
@@ -426,7 +540,7 @@ int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, const 
         L.seg_of[i] = k;
         if (key[i].direct < 0) ch[k] += cdiv(blocks[i], effective_bpf(items[i], sched[i]));
     }
-    L.cursor_bytes = align_up(64 * keys.size(), 256);
+    L.cursor_bytes = align_up(BATCH_SEG_CURSOR_BYTES * keys.size(), 256);
     L.run_bytes = align_up(L.cursor_bytes + run, 256);
     L.each_off = L.run_bytes;
     L.each_bytes = align_up(each, 256);
@@ -483,11 +597,12 @@ int pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, const DevI
 template <int CLS>
 void launch_group(uint32_t block, dim3 gr, hipStream_t s, const BatchDesc* descs, const uint32_t* cmap,
                   uint32_t chunks, uint32_t* cursor, uint32_t* err) {
+    const RangeTable t = range_table(gr.x, chunks);
     switch (block) {
-    case 64: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 64>), gr, dim3(64), 0, s, descs, cmap, chunks, cursor, err); break;
-    case 128: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 128>), gr, dim3(128), 0, s, descs, cmap, chunks, cursor, err); break;
-    case 256: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 256>), gr, dim3(256), 0, s, descs, cmap, chunks, cursor, err); break;
-    case 512: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 512>), gr, dim3(512), 0, s, descs, cmap, chunks, cursor, err); break;
+    case 64: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 64>), gr, dim3(64), 0, s, descs, cmap, chunks, cursor, err, t); break;
+    case 128: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 128>), gr, dim3(128), 0, s, descs, cmap, chunks, cursor, err, t); break;
+    case 256: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 256>), gr, dim3(256), 0, s, descs, cmap, chunks, cursor, err, t); break;
+    case 512: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 512>), gr, dim3(512), 0, s, descs, cmap, chunks, cursor, err, t); break;
     }
 }
 
@@ -599,7 +714,7 @@ int enqueue_run(spmd_batch* b, hipStream_t s) {
             }
             const BatchSegment& g = b->seg[k];
             int rc = g.direct >= 0 ? launch_direct(b, g.direct, gs)
-                                   : launch_segment(b, g, gs, descs, reinterpret_cast<uint32_t*>(b->ws + 64 * k), err);
+                                   : launch_segment(b, g, gs, descs, reinterpret_cast<uint32_t*>(b->ws + BATCH_SEG_CURSOR_BYTES * k), err);
             if (rc) return rc;
             if (fork) {
                 if ((e = hipEventRecord(b->ev_join[k], gs)) != hipSuccess) return hip_fail(e);

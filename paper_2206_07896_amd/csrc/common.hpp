@@ -19,6 +19,11 @@ enum : uint32_t {
     ERRBIT_QUEUE = 4u,        // a batch chunk fell outside its instance
 };
 
+// Fetch cursors of one batch queue segment in the run area: up to 8 chunk
+// ranges, one 32-bit cursor per 128-byte slot.
+constexpr size_t BATCH_CURSOR_RANGES = 8, BATCH_CURSOR_SLOT = 128;
+constexpr size_t BATCH_SEG_CURSOR_BYTES = BATCH_CURSOR_RANGES * BATCH_CURSOR_SLOT;
+
 struct DevInfo {
     int device;
     int num_cus;

@@ -119,11 +119,12 @@ int as_launched(const spmd_launch_desc& d, const spmd_batch_item& it, spmd_sched
 
 // Bound on the batch workspace over every schedule: the finest schedule
 // (64 threads, 1 item, 1 block per fetch) has the most blocks and chunks;
-// each further queue group can add one 256-byte alignment gap.
+// each further queue group (16 at most: 4 classes x 4 block sizes) can add
+// its cursors and one 256-byte alignment gap.
 size_t batch_bound(const std::vector<spmd_batch_item>& items) {
     std::vector<spmd_schedule> fine(items.size(), spmd_schedule{64, 1, 1});
     const size_t b = spmd_batch_workspace_size(items.data(), fine.data(), (int)items.size());
-    return b ? b + 16 * 256 : 0;
+    return b ? b + 16 * (BATCH_SEG_CURSOR_BYTES + 256) : 0;
 }
 
 struct InferLayout {

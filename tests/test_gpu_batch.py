@@ -264,6 +264,33 @@ def test_batch_hist_skew(spmd):
     b.close()
 
 
+@pytest.mark.parametrize("wpc", [0, 1])
+def test_batch_chunk_ranges(spmd, wpc):
+    """A segment's chunks are cut into up to 8 ranges, one cursor each, with
+    static first chunks and stealing across ranges.  One histogram instance
+    per batch, blockDim 64, 1 item, 1 block per fetch, so chunks = blocks:
+    counts around the range count (1, 3, 7, 8, 9) and around the worker pool
+    (all static, one dynamic chunk, several per worker), ragged last blocks."""
+    import torch
+
+    pool = spmd.batch.pool_size(spmd.HIST256_U32, 64, wpc)
+    counts = [1, 3, 7, 8, 9, pool - 1, pool, pool + 1, 3 * pool + 5]
+    for j, chunks in enumerate(counts):
+        n = 64 * (chunks - 1) + 17
+        x = synth.uniform_u32(90 + j, n)
+        inst = dict(kind="hist", kid=spmd.HIST256_U32, n=n, ny=1, x=x, tin=dev(x),
+                    tout=torch.full((256,), 77, dtype=torch.int32, device="cuda"), bd=64, sched=(64, 1, 1))
+        say("chunk ranges", wpc, chunks, "of pool", pool)
+        b = spmd.batch.Batch(items_of([inst]), [inst["sched"]], workers_per_cu=wpc)
+        assert b.stats()["chunks"] == chunks
+        for mode in ("eager", "graph", "graph"):
+            scribble([inst])
+            b.launch() if mode == "eager" else b.graph_launch()
+            spmd.sync()
+            check_all([inst], f"chunk ranges {chunks} {mode}")
+        b.close()
+
+
 @pytest.mark.parametrize("seed", [5])
 def test_batch_random_levels(spmd, seed):
     """Seeded instances with random dependencies (no data flows along them):
