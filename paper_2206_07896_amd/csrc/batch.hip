@@ -136,6 +136,36 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
     }
 }
 
+// JACOBI: the logical blocks of one chunk as a two-stage pipeline -- block
+// b+1's global loads are issued before block b's are waited on, so a
+// workgroup keeps two tiles' loads in flight.  (Two named register sets,
+// not an indexed pair, so nothing goes to scratch.)  Every cell is computed
+// as in jacobi_block.
+template <int B, int C>
+__device__ __forceinline__ void jacobi_chunk(const BatchDesc& d, uint32_t first, uint32_t last,
+                                             JacobiLds<64, B / 64, C>& L) {
+    constexpr int BY = B / 64;
+    const float* u = reinterpret_cast<const float*>(d.in);
+    float* v = reinterpret_cast<float*>(d.out);
+    const int tx = (int)(threadIdx.x & 63u), ty = (int)(threadIdx.x >> 6);
+    const uint32_t w = d.aux;  // blocks per row
+    JacobiRegs<64, BY, C> R0, R1;
+    jacobi_load<64, BY, C>(u, d.n, d.ny, first % w, first / w, tx, ty, R0);
+    for (uint32_t b = first; b < last; b += 2) {
+        if (b + 1 < last) jacobi_load<64, BY, C>(u, d.n, d.ny, (b + 1) % w, (b + 1) / w, tx, ty, R1);
+        jacobi_commit<64, BY, C>(tx, ty, R0, L);
+        __syncthreads();
+        jacobi_compute<64, BY, C>(v, d.n, d.ny, b % w, b / w, tx, ty, L);
+        __syncthreads();  // the next commit reuses the LDS tile
+        if (b + 1 >= last) break;
+        if (b + 2 < last) jacobi_load<64, BY, C>(u, d.n, d.ny, (b + 2) % w, (b + 2) / w, tx, ty, R0);
+        jacobi_commit<64, BY, C>(tx, ty, R1, L);
+        __syncthreads();
+        jacobi_compute<64, BY, C>(v, d.n, d.ny, (b + 1) % w, (b + 1) / w, tx, ty, L);
+        __syncthreads();
+    }
+}
+
 // REDUCE and HIST: the logical blocks of one fetch cover one contiguous
 // element range, so they share one block body -- one LDS sub-histogram
 // flushed once, one partial published once -- instead of paying the flush
@@ -329,9 +359,18 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
                 run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
                 __syncthreads();
             } else {
-                for (uint32_t b = first; b < last; ++b) {
-                    run_logical_block<CLS, B>(d, b, L, err, NoHook());
-                    __syncthreads();  // the next logical block reuses the LDS
+                switch (d.items) {
+                case 1: jacobi_chunk<B, 1>(d, first, last, L.j1); break;
+                case 2: jacobi_chunk<B, 2>(d, first, last, L.j2); break;
+                case 4: jacobi_chunk<B, 4>(d, first, last, L.j4); break;
+                default:
+                    // 8 cells per thread already keep about 9 loads in flight
+                    // per thread; a second register set would cost occupancy
+                    for (uint32_t b = first; b < last; ++b) {
+                        run_logical_block<CLS, B>(d, b, L, err, NoHook());
+                        __syncthreads();  // the next logical block reuses the LDS
+                    }
+                    break;
                 }
             }
             if (t < 64) {

@@ -19,42 +19,61 @@ struct JacobiLds {
     float t[BY * C + 2][BX + 2];
 };
 
+// A block's tile in three phases, so that a loop over blocks can issue one
+// block's loads before it waits on the previous block's: every global load
+// into registers, registers to the LDS tile (a barrier must follow), and
+// the cells from the LDS tile.
 template <int BX, int BY, int C>
-__device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
-                                             uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
-                                             JacobiLds<BX, BY, C>& L) {
-#pragma clang fp contract(off)
+struct JacobiRegs {
+    static constexpr int NP = (BY * C + 2 + BY - 1) / BY;  // row passes per thread
+    float vc[NP], vh[NP];                                 // interior column, halo column
+};
+
+template <int BX, int BY, int C>
+__device__ __forceinline__ void jacobi_load(const float* __restrict__ u, uint32_t nx, uint32_t ny, uint32_t bx,
+                                            uint32_t by, int tx, int ty, JacobiRegs<BX, BY, C>& R) {
     constexpr int TY = BY * C;
     constexpr int H = TY + 2;
-    constexpr int NP = (H + BY - 1) / BY;  // row passes per thread
+    constexpr int NP = JacobiRegs<BX, BY, C>::NP;
     const int64_t x0 = (int64_t)bx * BX, y0 = (int64_t)by * TY;
     const int64_t NX = nx, NY = ny;
-    // Every load of the tile and its halo is issued before the first LDS
-    // store, so each thread keeps NP (+NP halo) loads in flight.
     const int64_t gxc = x0 + tx;                     // interior column of this thread
     const int64_t gxh = tx == 0 ? x0 - 1 : x0 + BX;  // halo column (threads tx < 2)
     const bool has_c = gxc < NX;
     const bool has_h = tx < 2 && gxh >= 0 && gxh < NX;
-    float vc[NP], vh[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int r = ty + p * BY;
         const int64_t gy = y0 - 1 + r;
         const bool rowok = r < H && gy >= 0 && gy < NY;
-        vc[p] = (rowok && has_c) ? u[gy * NX + gxc] : 0.0f;
-        vh[p] = (rowok && has_h) ? u[gy * NX + gxh] : 0.0f;
+        R.vc[p] = (rowok && has_c) ? u[gy * NX + gxc] : 0.0f;
+        R.vh[p] = (rowok && has_h) ? u[gy * NX + gxh] : 0.0f;
     }
+}
+
+template <int BX, int BY, int C>
+__device__ __forceinline__ void jacobi_commit(int tx, int ty, const JacobiRegs<BX, BY, C>& R,
+                                              JacobiLds<BX, BY, C>& L) {
+    constexpr int H = BY * C + 2;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    for (int p = 0; p < JacobiRegs<BX, BY, C>::NP; ++p) {
         const int r = ty + p * BY;
         if (r < H) {
-            L.t[r][tx + 1] = vc[p];
-            if (tx < 2) L.t[r][tx == 0 ? 0 : BX + 1] = vh[p];
+            L.t[r][tx + 1] = R.vc[p];
+            if (tx < 2) L.t[r][tx == 0 ? 0 : BX + 1] = R.vh[p];
         }
     }
-    __syncthreads();
-    const int64_t gx = gxc;
-    if (!has_c) return;
+}
+
+template <int BX, int BY, int C>
+__device__ __forceinline__ void jacobi_compute(float* __restrict__ v, uint32_t nx, uint32_t ny, uint32_t bx,
+                                               uint32_t by, int tx, int ty, const JacobiLds<BX, BY, C>& L) {
+#pragma clang fp contract(off)
+    constexpr int TY = BY * C;
+    const int64_t x0 = (int64_t)bx * BX, y0 = (int64_t)by * TY;
+    const int64_t NX = nx, NY = ny;
+    const int64_t gx = x0 + tx;
+    if (gx >= NX) return;
     const bool xborder = (gx == 0) || (gx == NX - 1);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -73,6 +92,19 @@ __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float*
         }
         v[gy * NX + gx] = out;
     }
+}
+
+// One block: every load of the tile and its halo is issued before the
+// first LDS store, so each thread keeps NP (+NP halo) loads in flight.
+template <int BX, int BY, int C>
+__device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
+                                             uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
+                                             JacobiLds<BX, BY, C>& L) {
+    JacobiRegs<BX, BY, C> R;
+    jacobi_load<BX, BY, C>(u, nx, ny, bx, by, tx, ty, R);
+    jacobi_commit<BX, BY, C>(tx, ty, R, L);
+    __syncthreads();
+    jacobi_compute<BX, BY, C>(v, nx, ny, bx, by, tx, ty, L);
 }
 
 
