@@ -364,7 +364,7 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
                 case 2: jacobi_chunk<B, 2>(d, first, last, L.j2); break;
                 case 4: jacobi_chunk<B, 4>(d, first, last, L.j4); break;
                 default:
-                    // 8 cells per thread already keep about 9 loads in flight
+                    // 8 cells per thread already keep about 10 loads in flight
                     // per thread; a second register set would cost occupancy
                     for (uint32_t b = first; b < last; ++b) {
                         run_logical_block<CLS, B>(d, b, L, err, NoHook());

@@ -23,10 +23,16 @@ struct JacobiLds {
 // block's loads before it waits on the previous block's: every global load
 // into registers, registers to the LDS tile (a barrier must follow), and
 // the cells from the LDS tile.
+// The interior columns take NP row passes per thread.  The two halo
+// columns, 2H cells (H = BY*C + 2 rows), are spread over all threads: halo
+// cell i = t + k*BX*BY is row i/2 of the west (i even) or east (i odd)
+// column, NH = ceil(2H / threads) cells per thread (one for 64-wide blocks).
 template <int BX, int BY, int C>
 struct JacobiRegs {
-    static constexpr int NP = (BY * C + 2 + BY - 1) / BY;  // row passes per thread
-    float vc[NP], vh[NP];                                 // interior column, halo column
+    static constexpr int NP = (BY * C + 2 + BY - 1) / BY;          // row passes per thread
+    static constexpr int NH = (2 * (BY * C + 2) + BX * BY - 1) / (BX * BY);  // halo cells per thread
+    float vc[NP];                                                 // interior column
+    float vh[NH];                                                 // halo cells
 };
 
 template <int BX, int BY, int C>
@@ -35,19 +41,26 @@ __device__ __forceinline__ void jacobi_load(const float* __restrict__ u, uint32_
     constexpr int TY = BY * C;
     constexpr int H = TY + 2;
     constexpr int NP = JacobiRegs<BX, BY, C>::NP;
+    constexpr int NH = JacobiRegs<BX, BY, C>::NH;
     const int64_t x0 = (int64_t)bx * BX, y0 = (int64_t)by * TY;
     const int64_t NX = nx, NY = ny;
-    const int64_t gxc = x0 + tx;                     // interior column of this thread
-    const int64_t gxh = tx == 0 ? x0 - 1 : x0 + BX;  // halo column (threads tx < 2)
+    const int64_t gxc = x0 + tx;  // interior column of this thread
     const bool has_c = gxc < NX;
-    const bool has_h = tx < 2 && gxh >= 0 && gxh < NX;
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int r = ty + p * BY;
         const int64_t gy = y0 - 1 + r;
         const bool rowok = r < H && gy >= 0 && gy < NY;
         R.vc[p] = (rowok && has_c) ? u[gy * NX + gxc] : 0.0f;
-        R.vh[p] = (rowok && has_h) ? u[gy * NX + gxh] : 0.0f;
+    }
+    const int t = ty * BX + tx;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+        const int i = t + k * BX * BY;
+        const int64_t gxh = (i & 1) ? x0 + BX : x0 - 1;  // west (i even) or east column
+        const int64_t gyh = y0 - 1 + (i >> 1);
+        const bool has_h = i < 2 * H && gxh >= 0 && gxh < NX && gyh >= 0 && gyh < NY;
+        R.vh[k] = has_h ? u[gyh * NX + gxh] : 0.0f;
     }
 }
 
@@ -58,10 +71,13 @@ __device__ __forceinline__ void jacobi_commit(int tx, int ty, const JacobiRegs<B
 #pragma unroll
     for (int p = 0; p < JacobiRegs<BX, BY, C>::NP; ++p) {
         const int r = ty + p * BY;
-        if (r < H) {
-            L.t[r][tx + 1] = R.vc[p];
-            if (tx < 2) L.t[r][tx == 0 ? 0 : BX + 1] = R.vh[p];
-        }
+        if (r < H) L.t[r][tx + 1] = R.vc[p];
+    }
+    const int t = ty * BX + tx;
+#pragma unroll
+    for (int k = 0; k < JacobiRegs<BX, BY, C>::NH; ++k) {
+        const int i = t + k * BX * BY;
+        if (i < 2 * H) L.t[i >> 1][(i & 1) ? BX + 1 : 0] = R.vh[k];
     }
 }
 
@@ -95,7 +111,7 @@ __device__ __forceinline__ void jacobi_compute(float* __restrict__ v, uint32_t n
 }
 
 // One block: every load of the tile and its halo is issued before the
-// first LDS store, so each thread keeps NP (+NP halo) loads in flight.
+// first LDS store, so each thread keeps NP (+1 halo) loads in flight.
 template <int BX, int BY, int C>
 __device__ __forceinline__ void jacobi_block(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
                                              uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
