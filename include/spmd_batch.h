@@ -7,12 +7,14 @@
  * fetch itself is one atomic operation on the queue's cursor.  Here the
  * workers are resident workgroups, a cursor is a device counter advanced
  * with one relaxed device-scope atomic per fetch, and the queue is a table
- * of chunks (instance, first logical block) built on the host.  A scan
- * queue has one cursor, so its tiles start in order; any other queue cuts
- * its chunks into up to 8 contiguous ranges with a cursor each (workgroup
- * w serves range w mod 8, i.e. one XCD, and moves on to the other ranges
- * once its own is drained), which spreads the fetch atomics over 8
- * counters and keeps a range's data in one XCD's L2.  A batch is
+ * of chunks (instance, first logical block) built on the host.  A queue
+ * cuts its chunks into up to 8 contiguous ranges with a cursor each
+ * (workgroup w serves range w mod 8, i.e. one XCD, and moves on to the
+ * other ranges once its own is drained), which spreads the fetch atomics
+ * over 8 counters and keeps a range's data in one XCD's L2.  A scan queue
+ * cuts only at instance starts, and only when its tiles are small (4096
+ * elements or fewer on average); its tiles are all drawn, in order within
+ * an instance.  A batch is
  * prepared once (spmd_batch_create: descriptors and chunk tables uploaded,
  * optional hipGraph captured) and then run any number of times.
  *

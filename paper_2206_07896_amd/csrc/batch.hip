@@ -197,8 +197,8 @@ __device__ __forceinline__ void run_fused_chunk(const BatchDesc& d, uint32_t q, 
     }
 }
 
-// Chunk ranges of a segment whose chunks may run in any order (every class
-// but SCAN).  The chunks are cut into R = min(8, workers) contiguous ranges
+// Chunk ranges of a segment.  The chunks are cut into R = min(8, workers)
+// contiguous ranges
 // with one cursor each, 128 bytes apart.  Worker w belongs to range w mod R:
 // the hardware deals a grid's workgroups to the 8 XCDs round-robin, so a
 // range runs on one XCD and its instances' lines -- a stencil's neighbouring
@@ -212,8 +212,12 @@ __device__ __forceinline__ void run_fused_chunk(const BatchDesc& d, uint32_t q, 
 // exhausted the worker reads the other open ranges' cursors (one round of
 // plain loads, in parallel: a cursor only grows, so a range seen exhausted
 // stays so), draws from the next range still open, and exits when none is.
-// The host computes the table (range_table below) once per segment; the
-// kernel copies it to LDS, where wave 0 reads it at chunk ends.
+// A SCAN segment's ranges start at instance boundaries and have no static
+// chunks: every tile is drawn, so an instance's tiles start in order from
+// one cursor and a look-back only waits for tiles that running workers
+// already hold (range_table_ordered).
+// The host computes the table once per segment; the kernel copies it to
+// LDS, where wave 0 reads it at chunk ends.
 struct RangeTable {
     uint32_t lo[BATCH_CURSOR_RANGES + 1];   // first chunk of range q; lo[R] = the chunk count
     uint32_t wlo[BATCH_CURSOR_RANGES + 1];  // workers of ranges 0 .. q-1
@@ -221,6 +225,7 @@ struct RangeTable {
     uint32_t closed;                        // ranges with no chunk to draw, one bit each
 };
 
+// Ranges of a segment whose chunks may run in any order.
 RangeTable range_table(uint32_t workers, uint32_t chunks) {
     RangeTable t{};
     const uint32_t R = workers < BATCH_CURSOR_RANGES ? workers : (uint32_t)BATCH_CURSOR_RANGES;
@@ -231,6 +236,35 @@ RangeTable range_table(uint32_t workers, uint32_t chunks) {
     }
     for (uint32_t q = 0; q < R; ++q)
         if (t.lo[q + 1] - t.lo[q] <= t.wlo[q + 1] - t.wlo[q]) t.closed |= 1u << q;
+    return t;
+}
+
+// Ranges of a SCAN segment: cut at the first instance start at or after
+// each proportional point (cinst[i] is the instance of chunk i, chunks in
+// queue order), all chunks drawn (no static ones).  Only segments of small
+// tiles are cut (mean chunk <= SCAN_RANGES_MAX_ELEMS elements), where one
+// cursor's serialized draws bound the queue.  Large tiles keep one range:
+// measured on the mixed workload's scans, 8 ranges took 4.86 ms against
+// 7.11 at 2048-element tiles, were even at 4096 and lost at 8192 (2.79
+// against 2.47 ms).
+constexpr uint64_t SCAN_RANGES_MAX_ELEMS = 4096;
+
+RangeTable range_table_ordered(uint32_t workers, const std::vector<uint32_t>& cinst, uint64_t elems) {
+    RangeTable t{};
+    const uint32_t total = (uint32_t)cinst.size();
+    const bool cut = total && elems <= SCAN_RANGES_MAX_ELEMS * total;
+    const uint32_t R = !cut ? 1u : workers < BATCH_CURSOR_RANGES ? workers : (uint32_t)BATCH_CURSOR_RANGES;
+    t.nrange = R;
+    uint32_t i = 0;
+    for (uint32_t q = 0; q <= R; ++q) {
+        const uint32_t target = R ? (uint32_t)((uint64_t)total * q / R) : 0u;
+        if (i < target) i = target;
+        while (i < total && i > 0 && cinst[i] == cinst[i - 1]) ++i;
+        t.lo[q] = q == R ? total : i;
+        t.wlo[q] = 0;
+    }
+    for (uint32_t q = 0; q < R; ++q)
+        if (t.lo[q + 1] == t.lo[q]) t.closed |= 1u << q;
     return t;
 }
 
@@ -294,45 +328,54 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
     __shared__ uint32_t s_next;
     __shared__ RangeTable s_ranges;
     const uint32_t t = threadIdx.x;
+    if (t == 0) s_ranges = ranges;
+    __syncthreads();
+    ChunkRanges q(s_ranges, cursor);
     if constexpr (CLS == SPMD_SCAN_I32) {
-        // One cursor, every chunk drawn from it: tiles start in order and a
-        // tile is only ever owned by a running worker, so the tiles a
-        // look-back waits on are in progress even when other kernels hold
-        // some of the compute units.  The next draw is made once the tile
-        // has published its inclusive prefix: drawn earlier, a reserved
-        // tile that has not started would hold up its successors' look-back
-        // while this worker is itself waiting in a look-back.
-        if (t == 0) s_next = atomic_add_dev(cursor, 1u);
+        // Every tile is drawn (no static chunks), in order within its range,
+        // and a range holds whole instances: a tile is only ever owned by a
+        // running worker, so the tiles a look-back waits on are in progress
+        // even when other kernels hold some of the compute units.  The next
+        // draw is made once the tile has published its inclusive prefix:
+        // drawn earlier, a reserved tile that has not started would hold up
+        // its successors' look-back while this worker is itself waiting in a
+        // look-back.
+        if (t < 64) {
+            const bool drawn = q.open();
+            const uint32_t r = q.resolve(drawn && t == 0 ? q.draw() : 0u, drawn);
+            if (t == 0) s_next = r;
+        }
         __syncthreads();
         uint32_t c = __builtin_amdgcn_readfirstlane(s_next);
         while (c < total_chunks) {
             __syncthreads();  // every thread has read s_next
-            uint32_t nxt = 0;
-            bool fetched = false;
+            uint32_t raw = 0;
+            bool hooked = false;  // thread 0: the look-back hook has run
             const BatchDesc d = descs[chunk_inst[c]];
             const uint32_t first = (c - d.chunk0) * d.bpf;
             const uint32_t last = min(first + d.bpf, d.nblocks);
             if (t == 0 && (first >= last || d.cls != (uint32_t)CLS))
                 atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
             if (d.cls != (uint32_t)CLS) break;
-            auto fetch_once = [&]() {
-                if (!fetched) {
-                    nxt = atomic_add_dev(cursor, 1u);
-                    fetched = true;
+            auto fetch_once = [&]() {  // thread 0, after the tile's look-back
+                if (!hooked) {
+                    hooked = true;
+                    if (q.open()) raw = q.draw();
                 }
             };
             for (uint32_t b = first; b < last; ++b) {
                 run_logical_block<CLS, B>(d, b, L, err, fetch_once);
                 __syncthreads();  // the next logical block reuses the LDS
             }
-            if (t == 0) s_next = fetched ? nxt : atomic_add_dev(cursor, 1u);
+            if (t < 64) {
+                const bool drawn = __builtin_amdgcn_readfirstlane(hooked ? 1u : 0u) != 0u && q.open();
+                const uint32_t r = q.resolve(raw, drawn);
+                if (t == 0) s_next = r;
+            }
             __syncthreads();
             c = __builtin_amdgcn_readfirstlane(s_next);
         }
     } else {
-        if (t == 0) s_ranges = ranges;
-        __syncthreads();
-        ChunkRanges q(s_ranges, cursor);
         uint32_t c = __builtin_amdgcn_readfirstlane(q.first());  // block-uniform
         if (c >= total_chunks) {
             if (t < 64) {
@@ -408,6 +451,7 @@ struct BatchSegment {
     uint32_t chunks;   // chunks in its queue
     uint32_t grid;     // persistent workgroups
     int direct;        // an instance with bpf 0, run as its own grid; -1 for a queue
+    RangeTable ranges;  // its chunk ranges (queues only)
 };
 
 struct SegKey {
@@ -635,8 +679,7 @@ int pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, const DevI
 
 template <int CLS>
 void launch_group(uint32_t block, dim3 gr, hipStream_t s, const BatchDesc* descs, const uint32_t* cmap,
-                  uint32_t chunks, uint32_t* cursor, uint32_t* err) {
-    const RangeTable t = range_table(gr.x, chunks);
+                  uint32_t chunks, uint32_t* cursor, uint32_t* err, const RangeTable& t) {
     switch (block) {
     case 64: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 64>), gr, dim3(64), 0, s, descs, cmap, chunks, cursor, err, t); break;
     case 128: hipLaunchKernelGGL((batch_persistent_kernel<CLS, 128>), gr, dim3(128), 0, s, descs, cmap, chunks, cursor, err, t); break;
@@ -709,10 +752,10 @@ int launch_segment(const spmd_batch* b, const BatchSegment& g, hipStream_t gs, c
     const uint32_t block = SIZE_B[g.group % NSIZES];
     const dim3 gr(g.grid);
     switch (CLS_ID[g.group / NSIZES]) {
-    case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
-    case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
-    case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
-    case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, g.chunks, cursor, err); break;
+    case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
+    case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
+    case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
+    case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
@@ -889,15 +932,21 @@ int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sch
         delete b;
         return hip_fail(e);
     }
-    for (BatchSegment& g : b->seg) {
+    std::vector<uint64_t> seg_elems(nseg, 0);  // elements queued per segment
+    for (int i = 0; i < n; ++i) seg_elems[L.seg_of[i]] += items[i].n;
+    for (size_t k = 0; k < nseg; ++k) {
+        BatchSegment& g = b->seg[k];
         b->total_chunks += g.chunks;
         if (g.direct >= 0) continue;
         uint32_t pool = 0;
-        if ((rc = pool_size(CLS_ID[g.group / NSIZES], SIZE_B[g.group % NSIZES], workers_per_cu, di, &pool))) {
+        const int cls = CLS_ID[g.group / NSIZES];
+        if ((rc = pool_size(cls, SIZE_B[g.group % NSIZES], workers_per_cu, di, &pool))) {
             delete b;
             return rc;
         }
         g.grid = (uint32_t)std::min<uint64_t>(pool, g.chunks);
+        g.ranges = cls == SPMD_SCAN_I32 ? range_table_ordered(g.grid, cmap[k], seg_elems[k])
+                                        : range_table(g.grid, g.chunks);
     }
     // events for the levels that fork over two or more segments
     const uint32_t nlevels = b->seg.back().level + 1;
