@@ -291,6 +291,37 @@ def test_batch_chunk_ranges(spmd, wpc):
         b.close()
 
 
+@pytest.mark.parametrize("wpc", [0, 1])
+def test_batch_scan_ranges(spmd, wpc):
+    """Scan segments of small tiles are cut into chunk ranges at instance
+    starts, every tile drawn from its range's cursor in order.  Many
+    instances of ragged sizes plus one long instance (hundreds of tiles, so
+    look-backs run deep inside a range and a range boundary falls right
+    after it), at 64- and 256-element tiles; with one worker per CU the
+    ranges are drained by few workers and stolen from."""
+    import torch
+
+    rng = np.random.default_rng(31 + wpc)
+    sizes = [int(v) for v in rng.integers(1, 3000, 60)]
+    sizes[17] = 200_003
+    insts = []
+    for j, n in enumerate(sizes):
+        x = synth.uniform_int32(400 + j, n, 0, 100)
+        sched = (64, 1, 1) if j % 2 else (128, 2, 1)
+        insts.append(dict(kind="scan", kid=spmd.SCAN_I32, n=n, ny=1, x=x, tin=dev(x),
+                          tout=torch.zeros(n + 64, dtype=torch.int32, device="cuda"), bd=256, sched=sched))
+    say("scan ranges", wpc, len(insts), "instances")
+    b = spmd.batch.Batch(items_of(insts), [it["sched"] for it in insts], workers_per_cu=wpc)
+    for mode in ("eager", "graph", "graph"):
+        scribble(insts)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        check_all(insts, f"scan ranges {mode}")
+        for it in insts:  # nothing written past the end
+            assert (host(it["tout"])[it["n"]:] == -12345).all(), f"scan ranges {mode}: n={it['n']}"
+    b.close()
+
+
 @pytest.mark.parametrize("seed", [5])
 def test_batch_random_levels(spmd, seed):
     """Seeded instances with random dependencies (no data flows along them):
