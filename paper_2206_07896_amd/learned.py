@@ -397,7 +397,10 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
 
     sched_learned = [CANDIDATES[j] for j in choice_fb]
     sched_exh = [CANDIDATES[j] for j in exhaustive]
+    choice_ba = model.choose(specs_ho, slack=BATCH_SLACK)[0]  # SPMD_SCHED_LEARNED's rule, no fallback
+    chunks_ho = sched_chunks(specs_ho).astype(np.int64)
     ms_learned = batch_ms(sched_learned)
+    ms_learned_ba = batch_ms([CANDIDATES[j] for j in choice_ba])
     ms_heur = batch_ms(heur)
     ms_exh = batch_ms(sched_exh)
     del data_ho
@@ -422,7 +425,9 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
         "abs_log_error_chosen_median": round(float(np.median(pred_err)), 4),
         "per_class": per_class,
         "batch_ms_learned": round(ms_learned, 3), "batch_ms_heuristic": round(ms_heur, 3),
-        "batch_ms_exhaustive": round(ms_exh, 3),
+        "batch_ms_exhaustive": round(ms_exh, 3), "batch_ms_learned_batch_aware": round(ms_learned_ba, 3),
+        "chunks_learned": int(chunks_ho[np.arange(heldout_count), choice_fb].sum()),
+        "chunks_learned_batch_aware": int(chunks_ho[np.arange(heldout_count), choice_ba].sum()),
         "launches_per_s_learned": round(heldout_count / (ms_learned * 1e-3), 1),
         "launches_per_s_heuristic": round(heldout_count / (ms_heur * 1e-3), 1),
         "launches_per_s_exhaustive": round(heldout_count / (ms_exh * 1e-3), 1),
@@ -432,7 +437,7 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
     }
     log(f"c5: regret {res['regret_mean']:.3f} (with fallback {res['regret_mean_with_fallback']:.3f}, "
         f"rate {res['fallback_rate']:.2f}), heuristic {res['regret_mean_heuristic']:.3f}; batch ms learned "
-        f"{ms_learned:.2f} heuristic {ms_heur:.2f} exhaustive {ms_exh:.2f}")
+        f"{ms_learned:.2f} batch-aware {ms_learned_ba:.2f} heuristic {ms_heur:.2f} exhaustive {ms_exh:.2f}")
     model.tau = tau
     return res, model
 
