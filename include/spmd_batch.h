@@ -37,9 +37,10 @@ extern "C" {
 
 /* Schedule of one instance: how its work is cut into logical blocks and
  * fetched.  `block` threads per logical block (64, 128, 256 or 512);
- * `items` elements per thread (REDUCE, SCAN, HIST: 1, 2, 4, 8 or 16; JACOBI:
- * cells per thread down a column, 1, 2, 4 or 8, with blocks of 64 x
- * block/64 threads); `bpf` logical blocks per fetch (>= 1; a SCAN
+ * `items` elements per thread (REDUCE, HIST: 1, 2, 4, 8 or 16; SCAN: also
+ * 32, tiles held in registers that run in a queue of their own;
+ * JACOBI: cells per thread down a column, 1, 2, 4 or 8, with blocks of
+ * 64 x block/64 threads); `bpf` logical blocks per fetch (>= 1; a SCAN
  * instance always fetches one tile at a time, since the tiles of one fetch
  * run in sequence and its successor waits on the last of them).  bpf 0
  * takes the instance out of the queue: it runs as its class's own grid,
@@ -214,7 +215,8 @@ int spmd_launch_batch_report(spmd_batch_report* out);
 int spmd_model_load(const float* params, uint32_t k_models, const float* norm, float sd_threshold);
 
 /* The candidate schedules the tuner and the cost model range over, in
- * their fixed order (block 64..512, then items 1..16, then bpf 1..32);
+ * their fixed order (block 64..512, then items 1..32, then bpf 1..32; 144
+ * in all, items 32 valid for SCAN only, items above 8 not for JACOBI);
  * writes up to `cap` of them and returns how many there are. */
 uint32_t spmd_sched_candidates(spmd_schedule* out, uint32_t cap);
 

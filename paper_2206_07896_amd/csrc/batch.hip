@@ -61,10 +61,20 @@ static_assert(sizeof(BatchDesc) == 64, "descriptor is 64 bytes");
 
 // One queue per (class, block size): each persistent kernel then holds only
 // one class body, which keeps its register use -- and so the number of
-// resident workers -- at that class's own level.
-constexpr int NSIZES = 4, NCLS = 4, NGROUPS = NSIZES * NCLS;
+// resident workers -- at that class's own level.  Scans of 32 items per
+// thread have a queue class of their own, BATCH_SCAN_WIDE (a queue class,
+// never a launch's kernel id), so their tiles' registers do not lower the
+// occupancy of every scan schedule.  (A 64-item path in the same kernel
+// took it to 135 VGPRs, one 512-thread workgroup per CU; 32 items alone
+// need 87.)
+constexpr int BATCH_SCAN_WIDE = 101;
+constexpr int NSIZES = 4, NCLS = 5, NGROUPS = NSIZES * NCLS;
+constexpr int NLAUNCH_CLS = 4;  // CLS_ID[0..3] are launch kernel ids
 constexpr uint32_t SIZE_B[NSIZES] = {64, 128, 256, 512};
-constexpr int CLS_ID[NCLS] = {SPMD_REDUCE_I32, SPMD_SCAN_I32, SPMD_HIST256_U32, SPMD_JACOBI5_F32};
+constexpr int CLS_ID[NCLS] = {SPMD_REDUCE_I32, SPMD_SCAN_I32, SPMD_HIST256_U32, SPMD_JACOBI5_F32, BATCH_SCAN_WIDE};
+// the launch kernel id whose instances a queue class runs
+constexpr int served_by(int cls) { return cls == BATCH_SCAN_WIDE ? SPMD_SCAN_I32 : cls; }
+constexpr bool ordered_cls(int cls) { return served_by(cls) == SPMD_SCAN_I32; }
 
 template <int CLS, int B>
 struct BatchLdsOf;
@@ -81,6 +91,10 @@ struct BatchLdsOf<SPMD_SCAN_I32, B> {
         ScanLds<B, 8> s8;
         ScanLds<B, 16> s16;
     };
+};
+template <int B>
+struct BatchLdsOf<BATCH_SCAN_WIDE, B> {
+    ScanLds<B, 32> s32;
 };
 template <int B>
 struct BatchLdsOf<SPMD_HIST256_U32, B> {
@@ -117,6 +131,12 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
         case 8: scan_tile<B, 8>(x, y, d.n, b, st, 0u, err, v, L.s8, hook); break;
         default: scan_tile<B, 16>(x, y, d.n, b, st, 0u, err, v, L.s16, hook); break;
         }
+    } else if constexpr (CLS == BATCH_SCAN_WIDE) {
+        const int32_t* x = reinterpret_cast<const int32_t*>(d.in);
+        int32_t* y = reinterpret_cast<int32_t*>(d.out);
+        uint64_t* st = reinterpret_cast<uint64_t*>(d.ws);
+        const bool v = d.vec != 0u;
+        scan_tile<B, 32>(x, y, d.n, b, st, 0u, err, v, L.s32, hook);
     } else if constexpr (CLS == SPMD_HIST256_U32) {
         const uint64_t lo = (uint64_t)b * d.aux;
         const uint64_t hi = lo + d.aux < (uint64_t)d.n ? lo + d.aux : (uint64_t)d.n;
@@ -331,7 +351,8 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
     if (t == 0) s_ranges = ranges;
     __syncthreads();
     ChunkRanges q(s_ranges, cursor);
-    if constexpr (CLS == SPMD_SCAN_I32) {
+    constexpr uint32_t SERVED = (uint32_t)served_by(CLS);  // the descriptors' class
+    if constexpr (ordered_cls(CLS)) {
         // Every tile is drawn (no static chunks), in order within its range,
         // and a range holds whole instances: a tile is only ever owned by a
         // running worker, so the tiles a look-back waits on are in progress
@@ -354,9 +375,9 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
             const BatchDesc d = descs[chunk_inst[c]];
             const uint32_t first = (c - d.chunk0) * d.bpf;
             const uint32_t last = min(first + d.bpf, d.nblocks);
-            if (t == 0 && (first >= last || d.cls != (uint32_t)CLS))
+            if (t == 0 && (first >= last || d.cls != SERVED))
                 atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
-            if (d.cls != (uint32_t)CLS) break;
+            if (d.cls != SERVED) break;
             auto fetch_once = [&]() {  // thread 0, after the tile's look-back
                 if (!hooked) {
                     hooked = true;
@@ -395,9 +416,9 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
             const BatchDesc d = descs[chunk_inst[c]];
             const uint32_t first = (c - d.chunk0) * d.bpf;
             const uint32_t last = min(first + d.bpf, d.nblocks);
-            if (t == 0 && (first >= last || d.cls != (uint32_t)CLS))
+            if (t == 0 && (first >= last || d.cls != SERVED))
                 atomicOr(err, first >= last ? ERRBIT_QUEUE : ERRBIT_BAD_DESC);
-            if (d.cls != (uint32_t)CLS) break;
+            if (d.cls != SERVED) break;
             if constexpr (CLS == SPMD_REDUCE_I32 || CLS == SPMD_HIST256_U32) {
                 run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
                 __syncthreads();
@@ -497,12 +518,15 @@ int size_index(uint32_t block) {
     return -1;
 }
 int class_index(int kernel_id) {
-    for (int c = 0; c < NCLS; ++c)
+    for (int c = 0; c < NLAUNCH_CLS; ++c)
         if (CLS_ID[c] == kernel_id) return c;
     return -1;
 }
-int group_of(int kernel_id, uint32_t block) {
-    const int si = size_index(block), ci = class_index(kernel_id);
+// queue group of an instance under a schedule: (queue class, block size)
+int group_of(int kernel_id, uint32_t block, uint32_t items) {
+    const int si = size_index(block);
+    int ci = class_index(kernel_id);
+    if (kernel_id == SPMD_SCAN_I32 && items >= 32) ci = NLAUNCH_CLS;  // BATCH_SCAN_WIDE
     return (si < 0 || ci < 0) ? -1 : ci * NSIZES + si;
 }
 
@@ -523,13 +547,14 @@ uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // Logical blocks of an item under a schedule, 0 if the pair is invalid.
 uint64_t item_blocks(const spmd_batch_item& it, const spmd_schedule& s) {
-    if (group_of(it.kernel_id, s.block) < 0) return 0;
+    if (group_of(it.kernel_id, s.block, s.items) < 0) return 0;
     const uint64_t per = (uint64_t)s.block * s.items;
     switch (it.kernel_id) {
     case SPMD_REDUCE_I32:
     case SPMD_SCAN_I32:
     case SPMD_HIST256_U32: {
-        if (s.items != 1 && s.items != 2 && s.items != 4 && s.items != 8 && s.items != 16) return 0;
+        const bool wide = it.kernel_id == SPMD_SCAN_I32 && s.items == 32;
+        if (s.items != 1 && s.items != 2 && s.items != 4 && s.items != 8 && s.items != 16 && !wide) return 0;
         const uint64_t nb = cdiv(it.n, per);
         return nb ? nb : 1;
     }
@@ -608,7 +633,7 @@ int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, const 
         blocks[i] = nb;
         run += run_scratch(it, nb);
         each += each_scratch(it, nb);
-        key[i] = SegKey{L.level[i], group_of(it.kernel_id, s.block), is_direct(s) ? i : -1};
+        key[i] = SegKey{L.level[i], group_of(it.kernel_id, s.block, s.items), is_direct(s) ? i : -1};
         if (it.kernel_id == SPMD_HIST256_U32) ++nhist;
     }
     // segments in (level, group, queue first) order
@@ -667,6 +692,7 @@ int pool_size(int kernel_id, uint32_t block, uint32_t workers_per_cu, const DevI
     switch (kernel_id) {
     case SPMD_REDUCE_I32: rc = occupancy_b<SPMD_REDUCE_I32>(block, &nb); break;
     case SPMD_SCAN_I32: rc = occupancy_b<SPMD_SCAN_I32>(block, &nb); break;
+    case BATCH_SCAN_WIDE: rc = occupancy_b<BATCH_SCAN_WIDE>(block, &nb); break;
     case SPMD_HIST256_U32: rc = occupancy_b<SPMD_HIST256_U32>(block, &nb); break;
     case SPMD_JACOBI5_F32: rc = occupancy_b<SPMD_JACOBI5_F32>(block, &nb); break;
     }
@@ -754,6 +780,7 @@ int launch_segment(const spmd_batch* b, const BatchSegment& g, hipStream_t gs, c
     switch (CLS_ID[g.group / NSIZES]) {
     case SPMD_REDUCE_I32: launch_group<SPMD_REDUCE_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
     case SPMD_SCAN_I32: launch_group<SPMD_SCAN_I32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
+    case BATCH_SCAN_WIDE: launch_group<BATCH_SCAN_WIDE>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
     case SPMD_HIST256_U32: launch_group<SPMD_HIST256_U32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
     case SPMD_JACOBI5_F32: launch_group<SPMD_JACOBI5_F32>(block, gr, gs, descs, cmap, g.chunks, cursor, err, g.ranges); break;
     }
@@ -945,8 +972,8 @@ int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sch
             return rc;
         }
         g.grid = (uint32_t)std::min<uint64_t>(pool, g.chunks);
-        g.ranges = cls == SPMD_SCAN_I32 ? range_table_ordered(g.grid, cmap[k], seg_elems[k])
-                                        : range_table(g.grid, g.chunks);
+        g.ranges = ordered_cls(cls) ? range_table_ordered(g.grid, cmap[k], seg_elems[k])
+                                    : range_table(g.grid, g.chunks);
     }
     // events for the levels that fork over two or more segments
     const uint32_t nlevels = b->seg.back().level + 1;

@@ -22,16 +22,19 @@ using namespace spmd;
 namespace {
 
 constexpr uint32_t CAND_BLOCKS[4] = {64, 128, 256, 512};
-constexpr uint32_t CAND_ITEMS[5] = {1, 2, 4, 8, 16};
+constexpr uint32_t CAND_ITEMS[6] = {1, 2, 4, 8, 16, 32};
 constexpr uint32_t CAND_BPF[6] = {1, 2, 4, 8, 16, 32};
-constexpr uint32_t NCANDS = 4 * 5 * 6;
+constexpr uint32_t NCANDS = 4 * 6 * 6;
 static_assert(NCANDS <= SPMD_MLP_MAX_CANDS, "candidate table fits the choice kernel");
 
 spmd_schedule candidate(uint32_t j) {
-    return {CAND_BLOCKS[j / 30], CAND_ITEMS[(j / 6) % 5], CAND_BPF[j % 6]};
+    return {CAND_BLOCKS[j / 36], CAND_ITEMS[(j / 6) % 6], CAND_BPF[j % 6]};
 }
 
+// Jacobi takes at most 8 cells per thread; 32 items are scan tiles only
+// (register-resident, in a queue class of their own).
 bool candidate_valid(int kernel_id, const spmd_schedule& s) {
+    if (s.items > 16 && kernel_id != SPMD_SCAN_I32) return false;
     return !(kernel_id == SPMD_JACOBI5_F32 && s.items > 8);
 }
 
@@ -119,12 +122,13 @@ int as_launched(const spmd_launch_desc& d, const spmd_batch_item& it, spmd_sched
 
 // Bound on the batch workspace over every schedule: the finest schedule
 // (64 threads, 1 item, 1 block per fetch) has the most blocks and chunks;
-// each further queue group (16 at most: 4 classes x 4 block sizes) can add
-// its cursors and one 256-byte alignment gap.
+// each further queue group (20 at most: 5 queue classes -- the wide scan
+// included -- x 4 block sizes) can add its cursors and one 256-byte
+// alignment gap.
 size_t batch_bound(const std::vector<spmd_batch_item>& items) {
     std::vector<spmd_schedule> fine(items.size(), spmd_schedule{64, 1, 1});
     const size_t b = spmd_batch_workspace_size(items.data(), fine.data(), (int)items.size());
-    return b ? b + 16 * (BATCH_SEG_CURSOR_BYTES + 256) : 0;
+    return b ? b + 20 * (BATCH_SEG_CURSOR_BYTES + 256) : 0;
 }
 
 struct InferLayout {

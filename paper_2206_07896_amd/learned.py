@@ -73,7 +73,10 @@ def candidate_inputs() -> np.ndarray:
 
 
 def valid_candidates(kid: int) -> np.ndarray:
-    return np.array([not (kid == JACOBI5_F32 and it > 8) for _, it, _ in CANDIDATES], bool)
+    """Jacobi takes at most 8 cells per thread; 32 items are scan tiles
+    only."""
+    return np.array([not ((kid == JACOBI5_F32 and it > 8) or (kid != SCAN_I32 and it > 16))
+                     for _, it, _ in CANDIDATES], bool)
 
 
 def launch_features(spec) -> np.ndarray:
@@ -467,6 +470,8 @@ def contention_study(model=None, log2_sizes=(12, 14, 16, 18, 20, 22), reps=5, lo
     import synth
 
     tuner = Autotuner(reps=reps)
+    valid = np.nonzero(valid_candidates(HIST256_U32))[0]  # indices into CANDIDATES
+    cands = [CANDIDATES[j] for j in valid]
     dists = (("zipf0", 0.0), ("zipf1.1", 1.1), ("zipf2", 2.0), ("zipf3", 3.0), ("one bin", None))
     hist = torch.zeros(256, dtype=torch.int32, device="cuda")
     rows = []
@@ -481,17 +486,17 @@ def contention_study(model=None, log2_sizes=(12, 14, 16, 18, 20, 22), reps=5, lo
                 B.synth_zipf_u32(keys, synth.SEED_HIST ^ lg, torch.from_numpy(synth.zipf_cdf(alpha, 256)).cuda())
             item = (HIST256_U32, n, 1, 256, keys, hist)
             # two full sweeps, the faster of each: at ~10 us a single stall skews one timing
-            T[name] = np.minimum(tuner.time(item, CANDIDATES), tuner.time(item, CANDIDATES))
+            T[name] = np.minimum(tuner.time(item, cands), tuner.time(item, cands))
         spec = {"kid": HIST256_U32, "n": n, "nx": n, "ny": 1, "block_dim": 256}
-        chosen = int(model.choose([spec])[0][0]) if model is not None else None
+        chosen = int(np.nonzero(valid == int(model.choose([spec])[0][0]))[0][0]) if model is not None else None
         ref = int(np.argmin(T["zipf1.1"]))
         for name, _ in dists:
             t = T[name]
             j = int(np.argmin(t))
-            row = {"log2_n": lg, "keys": name, "best_us": round(float(t[j]) * 1e3, 2), "best": list(CANDIDATES[j]),
+            row = {"log2_n": lg, "keys": name, "best_us": round(float(t[j]) * 1e3, 2), "best": list(cands[j]),
                    "regret_of_zipf1.1_best": round(float(t[ref] / t[j] - 1.0), 4)}
             if chosen is not None:
-                row["model"] = list(CANDIDATES[chosen])
+                row["model"] = list(cands[chosen])
                 row["regret_of_model"] = round(float(t[chosen] / t[j] - 1.0), 4)
             rows.append(row)
             if log is not None:

@@ -161,11 +161,11 @@ def test_schedule_candidates_table(spmd):
     from paper_2206_07896_amd import batch as B
 
     c = B.sched_candidates()
-    assert len(c) == 120 and len(set(c)) == 120
-    assert c[0] == (64, 1, 1) and c[-1] == (512, 16, 32)
+    assert len(c) == 144 and len(set(c)) == 144
+    assert c[0] == (64, 1, 1) and c[-1] == (512, 32, 32)
     assert sorted(c) == c  # block, then items, then bpf ascending
     assert {b for b, _, _ in c} == {64, 128, 256, 512}
-    assert {i for _, i, _ in c} == {1, 2, 4, 8, 16}
+    assert {i for _, i, _ in c} == {1, 2, 4, 8, 16, 32}
     assert {f for _, _, f in c} == {1, 2, 4, 8, 16, 32}
 
 
@@ -256,14 +256,15 @@ def test_launch_batch_workspace_covers_every_schedule(spmd):
     for c in cands:
         sch = (B.Schedule * len(items))(*[B.Schedule(*c) for _ in items])
         need = lib.spmd_batch_workspace_size(iarr, sch, len(items))
-        if need == 0:  # candidate invalid for a class (JACOBI items > 8)
+        if need == 0:  # candidate invalid for a class (JACOBI items > 8; items > 16 scan only)
             assert c[1] > 8
             continue
         assert need <= bound, (c, need, bound)
     # and for a random mix of per-launch schedules
     for _ in range(50):
         pick = [cands[int(j)] for j in rng.integers(0, len(cands), len(items))]
-        pick = [(b, min(it, 8) if items[k].kernel_id == spmd.JACOBI5_F32 else it, f)
+        pick = [(b, min(it, 8) if items[k].kernel_id == spmd.JACOBI5_F32 else
+                 it if items[k].kernel_id == spmd.SCAN_I32 else min(it, 16), f)
                 for k, (b, it, f) in enumerate(pick)]
         sch = (B.Schedule * len(items))(*[B.Schedule(*c) for c in pick])
         need = lib.spmd_batch_workspace_size(iarr, sch, len(items))
@@ -312,7 +313,10 @@ def test_sched_chunks_closed_forms(spmd):
     assert ch.shape == (3, len(C))
     for j, (blk, it, bpf) in enumerate(C):
         nb = -(-100000 // (blk * it))
-        assert ch[0, j] == -(-nb // bpf), (blk, it, bpf)
+        if it > 16:
+            assert ch[0, j] == 0xFFFFFFFF                       # 32 items: scan only
+        else:
+            assert ch[0, j] == -(-nb // bpf), (blk, it, bpf)
         assert ch[1, j] == nb                                   # scan: one tile per chunk
         if it > 8:
             assert ch[2, j] == 0xFFFFFFFF                       # Jacobi takes at most 8 cells per thread

@@ -322,6 +322,40 @@ def test_batch_scan_ranges(spmd, wpc):
     b.close()
 
 
+def test_batch_wide_scan(spmd):
+    """Scans of 32 items per thread run in a queue class of their own, side
+    by side with ordinary scan tiles in the same level: ragged and aligned
+    sizes, a misaligned view (the item path), all four block sizes."""
+    import torch
+
+    cases = [(1, (64, 32, 1)), (2047, (64, 32, 4)), (2048, (64, 32, 1)), (100_003, (128, 32, 1)),
+             (1 << 20, (256, 32, 2)), ((1 << 20) + 3, (512, 32, 1)), (300_001, (512, 16, 1)),
+             (65_537, (256, 8, 1)), (50_000, (512, 32, 1))]
+    insts = []
+    for j, (n, sched) in enumerate(cases):
+        x = synth.uniform_int32(500 + j, n, -(2**31), 2**31 - 1)
+        if j == 8:  # input one element into its buffer: not 16-byte aligned
+            buf = dev(np.concatenate([np.zeros(1, np.int32), x]))
+            tin = buf[1:]
+        else:
+            tin = dev(x)
+        insts.append(dict(kind="scan", kid=spmd.SCAN_I32, n=n, ny=1, x=x, tin=tin,
+                          tout=torch.zeros(n + 64, dtype=torch.int32, device="cuda"), bd=256, sched=sched))
+    say("wide scan", [it["sched"] for it in insts])
+    b = spmd.batch.Batch(items_of(insts), [it["sched"] for it in insts])
+    for mode in ("eager", "graph", "graph"):
+        scribble(insts)
+        b.launch() if mode == "eager" else b.graph_launch()
+        spmd.sync()
+        check_all(insts, f"wide scan {mode}")
+        for it in insts:
+            assert (host(it["tout"])[it["n"]:] == -12345).all(), f"wide scan {mode}: n={it['n']}"
+    b.launch_each()
+    spmd.sync()
+    check_all(insts, "wide scan, one launch per instance")
+    b.close()
+
+
 @pytest.mark.parametrize("seed", [5])
 def test_batch_random_levels(spmd, seed):
     """Seeded instances with random dependencies (no data flows along them):
