@@ -173,7 +173,7 @@ enum {
 
 /* Slack of the batch-aware learned choice: 20% over the least predicted
  * time buys fewer chunks to fetch (measured on the 10 000-launch mixed
- * queue: 6.8 ms against 7.8 ms for the least predicted time per launch). */
+ * queue: 6.3 ms against 8.8 ms for the least predicted time per launch). */
 #define SPMD_BATCH_SLACK 0.2f
 
 /* Chunk counts of n launches under every candidate schedule (the order of
