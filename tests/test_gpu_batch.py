@@ -58,7 +58,8 @@ def make_instances(spmd, count, seed, nmax_log2=16, include_edges=True):
         if include_edges and i < 16:
             n = [0, 1, 3, 64, 65, 257, 1000, 4099][i // 2 % 8] if kind != "jacobi" else [1, 2, 3, 5][i % 4]
         bd = int(rng.choice([64, 128, 256, 512]))
-        items = int(rng.choice([1, 2, 4, 8] if kind == "jacobi" else [1, 2, 4, 8, 16]))
+        items = int(rng.choice([1, 2, 4, 8] if kind == "jacobi" else [1, 2, 4, 8, 16, 32] if kind == "scan"
+                               else [1, 2, 4, 8, 16]))
         bpf = int(rng.choice([1, 2, 3, 8, 32]))
         s = 1000 + 7 * i + seed
         if kind == "reduce":
