@@ -223,4 +223,90 @@ __device__ __forceinline__ void jacobi_block_v4(const float* __restrict__ u, flo
     }
 }
 
+// General-width form, for any nx and alignment: a workgroup of 64 x BY
+// threads owns 256 columns and BY*C rows; thread tx holds columns tx,
+// tx + 64, tx + 128 and tx + 192 of the tile (a wave's four loads of one row
+// cover 1 KiB contiguous) and C rows, BY rows apart.  The interior sits at
+// LDS columns 1..256, the halo at 0 and 257; the halo cells are spread over
+// all threads.  Each cell is computed exactly as in jacobi_block.
+constexpr int JW_LD = JV_W + 2;
+
+template <int BY, int C>
+struct JacobiWLds {
+    float t[BY * C + 2][JW_LD];
+};
+
+template <int BY, int C>
+__device__ __forceinline__ void jacobi_block_w(const float* __restrict__ u, float* __restrict__ v, uint32_t nx,
+                                               uint32_t ny, uint32_t bx, uint32_t by, int tx, int ty,
+                                               JacobiWLds<BY, C>& L) {
+#pragma clang fp contract(off)
+    constexpr int TY = BY * C;
+    constexpr int H = TY + 2;
+    constexpr int NP = (H + BY - 1) / BY;
+    constexpr int T = 64 * BY;
+    constexpr int NH = (2 * H + T - 1) / T;
+    const int64_t x0 = (int64_t)bx * JV_W, y0 = (int64_t)by * TY;
+    const int64_t NX = nx, NY = ny;
+    float vc[NP][4], vh[NH];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
+        const int64_t gy = y0 - 1 + r;
+        const bool rowok = r < H && gy >= 0 && gy < NY;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t gx = x0 + tx + 64 * q;
+            vc[p][q] = (rowok && gx < NX) ? u[gy * NX + gx] : 0.0f;
+        }
+    }
+    const int t = ty * 64 + tx;
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+        const int i = t + k * T;
+        const int64_t gxh = (i & 1) ? x0 + JV_W : x0 - 1;  // east (i odd) or west column
+        const int64_t gyh = y0 - 1 + (i >> 1);
+        const bool has_h = i < 2 * H && gxh >= 0 && gxh < NX && gyh >= 0 && gyh < NY;
+        vh[k] = has_h ? u[gyh * NX + gxh] : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int r = ty + p * BY;
+        if (r < H) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L.t[r][1 + tx + 64 * q] = vc[p][q];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NH; ++k) {
+        const int i = t + k * T;
+        if (i < 2 * H) L.t[i >> 1][(i & 1) ? JV_W + 1 : 0] = vh[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int r = ty + k * BY;
+        const int64_t gy = y0 + r;
+        if (gy >= NY) break;
+        const bool yborder = gy == 0 || gy == NY - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t gx = x0 + tx + 64 * q;
+            if (gx >= NX) break;
+            const int lx = 1 + tx + 64 * q;
+            const float c = L.t[r + 1][lx];
+            float out;
+            if (yborder || gx == 0 || gx == NX - 1) {
+                out = c;
+            } else {
+                const float ns = L.t[r][lx] + L.t[r + 2][lx];
+                const float we = L.t[r + 1][lx - 1] + L.t[r + 1][lx + 1];
+                const float sum = ns + we;
+                out = 0.25f * sum;
+            }
+            v[gy * NX + gx] = out;
+        }
+    }
+}
+
 }  // namespace spmd

@@ -19,6 +19,15 @@ __global__ __launch_bounds__(64 * BY) void jacobi5_v4_kernel(const float* __rest
     jacobi_block_v4<BY, C>(u, v, nx, ny, t % gridDim.x, t / gridDim.x, threadIdx.x, threadIdx.y, L);
 }
 
+template <int BY, int C>
+__global__ __launch_bounds__(64 * BY) void jacobi5_w_kernel(const float* __restrict__ u, float* __restrict__ v,
+                                                            uint32_t nx, uint32_t ny) {
+    __shared__ JacobiWLds<BY, C> L;
+    const uint32_t nt = gridDim.x * gridDim.y;
+    const uint32_t t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, nt);
+    jacobi_block_w<BY, C>(u, v, nx, ny, t % gridDim.x, t / gridDim.x, threadIdx.x, threadIdx.y, L);
+}
+
 template <int BX, int BY>
 static void launch_c(uint32_t C, dim3 g, size_t dyn, hipStream_t s, const float* u, float* v, uint32_t nx,
                      uint32_t ny) {
@@ -48,20 +57,37 @@ int launch_jacobi5_f32(const LaunchCtx& c) {
     dim3 g(c.grid.x, c.grid.y);
     const size_t d = c.dyn_shmem;
     const uint64_t brow = (uint64_t)BY * C;  // rows of one block row of the launch
-    if (nx % 4u == 0 && aligned(u, 16) && aligned(v, 16) && brow >= 4 && brow <= 64) {
+    if (brow >= 4 && brow <= 64) {
         // The blocks of one block row are fetched 256 columns at a time
         // (coarse-grained fetching along x, Section IV-A) and run as one
-        // workgroup of 64 x 4 threads, four columns per thread: 16-byte
-        // loads and stores, the same rows as the launch's blocks, every
-        // cell computed as in its own block.
+        // workgroup of 64 x 4 threads, four columns per thread, the same
+        // rows as the launch's blocks, every cell computed as in its own
+        // block: 16-byte loads and stores when nx is a multiple of 4 and
+        // the rows are 16-byte aligned, else four 4-byte columns 64 apart.
+        const bool vec = nx % 4u == 0 && aligned(u, 16) && aligned(v, 16);
         const dim3 gv((nx + JV_W - 1) / JV_W, c.grid.y), bv(64, 4);
         hipStream_t st = c.stream;
         switch (brow) {
-        case 4: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny); break;
-        case 8: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny); break;
-        case 16: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny); break;
-        case 32: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny); break;
-        case 64: hipLaunchKernelGGL((jacobi5_v4_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny); break;
+        case 4:
+            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
+            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
+            break;
+        case 8:
+            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
+            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
+            break;
+        case 16:
+            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
+            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
+            break;
+        case 32:
+            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
+            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
+            break;
+        case 64:
+            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
+            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
+            break;
         }
         hipError_t e = hipGetLastError();
         return e == hipSuccess ? SPMD_OK : hip_fail(e);

@@ -217,7 +217,9 @@ SHAPES = [(16, 16), (32, 8), (64, 4), (64, 8), (128, 2), (128, 4), (256, 1)]
 @pytest.mark.parametrize("block", SHAPES)
 @pytest.mark.parametrize("cells", [1, 4])
 def test_jacobi_one_sweep(spmd, block, cells):
-    # nx % 4 == 0 takes the 16-byte (four columns per thread) form, the rest the scalar one
+    # Block rows of 4 to 64 rows run 256 columns per workgroup: nx % 4 == 0 with aligned rows
+    # takes the 16-byte form, any other nx the general-width form (four columns 64 apart);
+    # block rows of 1 or 2 rows take the scalar body.
     for (ny, nx) in [(33, 70), (130, 257), (3, 3), (33, 68), (130, 520), (5, 4), (64, 260)]:
         say("jacobi", ny, nx, block, cells)
         u = synth.uniform_f32(synth.SEED_JACOBI + nx, ny * nx).reshape(ny, nx)
@@ -225,6 +227,22 @@ def test_jacobi_one_sweep(spmd, block, cells):
         got = host(spmd.ops.jacobi5_f32(dev(u), block=block, cells=cells))
         spmd.sync()
         assert np.array_equal(got, want)
+
+
+def test_jacobi_misaligned_rows(spmd):
+    """nx a multiple of 4 but the grid one float into its buffer: rows are
+    not 16-byte aligned, so the general-width form runs."""
+    import torch
+
+    ny, nx = 70, 260
+    say("jacobi misaligned rows", ny, nx)
+    u = synth.uniform_f32(77, ny * nx).reshape(ny, nx)
+    buf = torch.zeros(ny * nx + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(u).reshape(-1)
+    out = torch.zeros(ny * nx + 1, dtype=torch.float32, device="cuda")
+    spmd.ops.jacobi5_f32(buf[1:].view(ny, nx), out=out[1:].view(ny, nx), block=(64, 4), cells=4)
+    spmd.sync()
+    assert np.array_equal(host(out[1:]).reshape(ny, nx), oracle.jacobi5_f32(u, 16, 16))
 
 
 @pytest.mark.parametrize("nx", [517, 516])
