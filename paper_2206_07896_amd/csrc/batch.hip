@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "cls_hist.hpp"
@@ -100,6 +101,11 @@ template <int B>
 struct BatchLdsOf<SPMD_HIST256_U32, B> {
     HistLds<HIST_COPIES> h;
 };
+// the 256-column tile of blocks of 256 or 512 threads; nothing for smaller
+// blocks, which run only 64-column blocks
+template <int B, int C>
+using WideJacobiLds = std::conditional_t<(B >= 256), JacobiWLds<B / 64, C>, char>;
+
 template <int B>
 struct BatchLdsOf<SPMD_JACOBI5_F32, B> {
     union {
@@ -107,6 +113,9 @@ struct BatchLdsOf<SPMD_JACOBI5_F32, B> {
         JacobiLds<64, B / 64, 2> j2;
         JacobiLds<64, B / 64, 4> j4;
         JacobiLds<64, B / 64, 8> j8;
+        WideJacobiLds<B, 1> w1;  // 256-column groups (blocks of 256 and 512 threads only)
+        WideJacobiLds<B, 2> w2;
+        WideJacobiLds<B, 4> w4;
     };
 };
 
@@ -183,6 +192,35 @@ __device__ __forceinline__ void jacobi_chunk(const BatchDesc& d, uint32_t first,
         __syncthreads();
         jacobi_compute<64, BY, C>(v, d.n, d.ny, (b + 1) % w, (b + 1) / w, tx, ty, L);
         __syncthreads();
+    }
+}
+
+// JACOBI, blocks of 256 or 512 threads: inside a chunk, every run of up to
+// four 64-column blocks of one row that starts at a multiple of four
+// columns-of-blocks and lies wholly in the chunk runs as one 256-column
+// tile of the general-width form (jacobi_block_w: each thread four columns
+// 64 apart, a wave's loads of a row 1 KiB contiguous); other blocks run one
+// by one.  Every cell is computed as in jacobi_block.
+template <int B, int C>
+__device__ __forceinline__ void jacobi_chunk_grouped(const BatchDesc& d, uint32_t first, uint32_t last,
+                                                     JacobiLds<64, B / 64, C>& L64, JacobiWLds<B / 64, C>& LW) {
+    constexpr int BY = B / 64;
+    const float* u = reinterpret_cast<const float*>(d.in);
+    float* v = reinterpret_cast<float*>(d.out);
+    const int tx = (int)(threadIdx.x & 63u), ty = (int)(threadIdx.x >> 6);
+    const uint32_t w = d.aux;  // 64-column blocks per row
+    uint32_t b = first;
+    while (b < last) {
+        const uint32_t bx = b % w, by = b / w;
+        const uint32_t run = min(4u, w - bx);  // blocks of this 256-column group in the row
+        if ((bx & 3u) == 0u && b + run <= last) {
+            jacobi_block_w<BY, C>(u, v, d.n, d.ny, bx >> 2, by, tx, ty, LW);
+            b += run;
+        } else {
+            jacobi_block<64, BY, C>(u, v, d.n, d.ny, bx, by, tx, ty, L64);
+            b += 1;
+        }
+        __syncthreads();  // the next tile reuses the LDS
     }
 }
 
@@ -423,7 +461,19 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
                 run_fused_chunk<CLS, B>(d, c - d.chunk0, first, last, L, err);
                 __syncthreads();
             } else {
-                switch (d.items) {
+                if constexpr (B >= 256) {
+                    switch (d.items) {
+                    case 1: jacobi_chunk_grouped<B, 1>(d, first, last, L.j1, L.w1); break;
+                    case 2: jacobi_chunk_grouped<B, 2>(d, first, last, L.j2, L.w2); break;
+                    case 4: jacobi_chunk_grouped<B, 4>(d, first, last, L.j4, L.w4); break;
+                    default:
+                        for (uint32_t b = first; b < last; ++b) {
+                            run_logical_block<CLS, B>(d, b, L, err, NoHook());
+                            __syncthreads();  // the next logical block reuses the LDS
+                        }
+                        break;
+                    }
+                } else switch (d.items) {
                 case 1: jacobi_chunk<B, 1>(d, first, last, L.j1); break;
                 case 2: jacobi_chunk<B, 2>(d, first, last, L.j2); break;
                 case 4: jacobi_chunk<B, 4>(d, first, last, L.j4); break;
