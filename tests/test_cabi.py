@@ -169,6 +169,24 @@ def test_schedule_candidates_table(spmd):
     assert {f for _, _, f in c} == {1, 2, 4, 8, 16, 32}
 
 
+def test_candidate_validity_matches_library(spmd):
+    """The binding's per-class candidate mask (what the tuner sweeps and
+    the cost model may choose) is exactly the set of candidates the
+    library's chunk table accepts: Jacobi at most 8 items, 32 items for
+    scan only."""
+    from paper_2206_07896_amd import learned as L
+
+    for kid in (spmd.REDUCE_I32, spmd.SCAN_I32, spmd.HIST256_U32, spmd.JACOBI5_F32):
+        nx, ny = (300, 200) if kid == spmd.JACOBI5_F32 else (100000, 1)
+        ch = L.sched_chunks([{"kid": kid, "nx": nx, "ny": ny, "block_dim": 256}])[0]
+        lib_ok = ch != 0xFFFFFFFF
+        assert np.array_equal(L.valid_candidates(kid), lib_ok), kid
+    items = np.array([it for _, it, _ in L.CANDIDATES])
+    assert not L.valid_candidates(spmd.JACOBI5_F32)[items > 8].any()
+    assert L.valid_candidates(spmd.SCAN_I32)[items == 32].all()
+    assert not L.valid_candidates(spmd.REDUCE_I32)[items == 32].any()
+
+
 def test_launch_features_closed_forms(spmd):
     from paper_2206_07896_amd import batch as B
 
