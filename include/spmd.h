@@ -91,7 +91,7 @@ enum {
      * grid (G,1,1), block (B,1,1), B in {64,128,256,512,1024}.  Block g
      * (in the order blocks start) scans a tile of B*I consecutive elements,
      * I = the smallest power of two >= ceil(n / (G*B)); I <= 32 (I <= 64 for B <= 512).
-     * x and y may not overlap. */
+     * x and y may not overlap (SPMD_ERR_ARGS). */
     SPMD_SCAN_I32 = 2,
 
     /* 256-bin histogram of keys & 255 with per-block LDS sub-histograms
@@ -164,7 +164,8 @@ enum {
      * ceil(n / (G*B)), I <= 32 (I <= 64 for B <= 512).  workspace:
      * spmd_workspace_size() bytes,
      * 16-byte aligned, zero-filled before first use, then reusable as for
-     * SCAN.  y must hold n elements. */
+     * SCAN.  y must hold n elements; x may overlap neither y nor count
+     * (SPMD_ERR_ARGS). */
     SPMD_COMPACT_I32 = 8,
 
     /* S fused sweeps of the SPMD_JACOBI5_F32 stencil in one pass over HBM
@@ -200,12 +201,28 @@ size_t spmd_workspace_size(int kernel_id, spmd_dim3 grid, spmd_dim3 block, uint6
 
 /* Wait for all work on `stream`, then read and clear this device's error
  * word: SPMD_ERR_DEVICE if a kernel set it since the last sync (the paper's
- * host waits on a condition variable until the queue drains, Section IV). */
+ * host waits on a condition variable until the queue drains, Section IV).
+ * The error word is one per device, not per stream: a sync on any stream
+ * reports -- and clears -- an error raised by any of the library's kernels
+ * on the device since the last sync, including one raised by a kernel of
+ * another stream that is still running.  A caller that needs to know which
+ * stream failed synchronises one stream at a time. */
 int spmd_sync(void* stream);
 
 /* spmd_sync with a bound: polls the stream until it is idle or `ms`
- * milliseconds have passed (SPMD_ERR_TIMEOUT; the work keeps running). */
+ * milliseconds have passed (SPMD_ERR_TIMEOUT; the work keeps running and
+ * the error word is left as it is, for a later sync to read). */
 int spmd_sync_timeout(void* stream, uint32_t ms);
+
+/* Bound on every cross-block wait of the library's kernels on the current
+ * device (a scan's look-back, the reduction's final gather), in polls of
+ * the awaited word; 0 restores the default (2^22 polls, seconds).  A wait
+ * that reaches the bound stops waiting, treats the missing value as zero
+ * and sets the device error word (SPMD_ERR_DEVICE at the next sync), so a
+ * kernel whose partner blocks never publish still ends.  Set
+ * synchronously; it applies to launches made after the call.  For failure
+ * detection: a short bound turns a stalled wait into a prompt error. */
+int spmd_set_spin_limit(uint32_t polls);
 
 /* Parameter kinds of a class as a string, one character per args[] entry:
  * 'p' device pointer, 'u' uint32_t.  NULL for an unknown id. */

@@ -57,9 +57,10 @@ typedef struct {
  * SPMD_HIST256_U32 or SPMD_JACOBI5_F32; `n` elements (JACOBI: nx columns),
  * `ny` rows for JACOBI (1 otherwise).  `in` is x / keys / u; `out` is the
  * int32 total (REDUCE), y[n] (SCAN), the 256 uint32 bins (HIST, overwritten)
- * or u_next (JACOBI, one sweep).  `block_dim` is the blockDim the instance
- * was written for; it is a feature of the instance, not a constraint on its
- * schedule. */
+ * or u_next (JACOBI, one sweep).  `out` may not overlap `in`
+ * (SPMD_ERR_ARGS): a plan may run an instance more than once.  `block_dim`
+ * is the blockDim the instance was written for; it is a feature of the
+ * instance, not a constraint on its schedule. */
 typedef struct {
     int32_t kernel_id;
     uint32_t n;
@@ -95,9 +96,11 @@ int spmd_batch_create(const spmd_batch_item* items, const spmd_schedule* sched, 
  * kernel per (class, block size) queue present in it, so a chain such as
  * 100 Jacobi sweeps is one batch, one graph, and no host round trip.  An
  * instance may read from several earlier instances as long as they all sit
- * below its level (levels are ordered as a whole).  dep[i] >= i (including
- * a self-dependency) is SPMD_ERR_ARGS.  Without dependencies the result is
- * the plain create's. */
+ * below its level (levels are ordered as a whole).  A HIST instance's bins
+ * are cleared in stream order just before its own level, so an instance of
+ * a lower level still reads what the bins held before.  dep[i] >= i
+ * (including a self-dependency) is SPMD_ERR_ARGS.  Without dependencies the
+ * result is the plain create's. */
 #define SPMD_NO_DEP 0xFFFFFFFFu
 
 size_t spmd_batch_workspace_size_dep(const spmd_batch_item* items, const spmd_schedule* sched, const uint32_t* dep,

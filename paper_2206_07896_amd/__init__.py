@@ -80,6 +80,8 @@ _lib.spmd_sync.argtypes = [_P]
 _lib.spmd_sync.restype = ctypes.c_int
 _lib.spmd_sync_timeout.argtypes = [_P, ctypes.c_uint32]
 _lib.spmd_sync_timeout.restype = ctypes.c_int
+_lib.spmd_set_spin_limit.argtypes = [ctypes.c_uint32]
+_lib.spmd_set_spin_limit.restype = ctypes.c_int
 _lib.spmd_kernel_signature.argtypes = [ctypes.c_int]
 _lib.spmd_kernel_signature.restype = ctypes.c_char_p
 _lib.spmd_kernel_name.argtypes = [ctypes.c_int]
@@ -172,6 +174,12 @@ def sync(stream=None) -> None:
 
 def sync_timeout(stream=None, ms: int = 10000) -> None:
     _check(_lib.spmd_sync_timeout(_stream_handle(stream), ms), "spmd_sync_timeout")
+
+
+def set_spin_limit(polls: int) -> None:
+    """Bound on cross-block waits of the current device, in polls (0: the
+    default); see spmd_set_spin_limit."""
+    _check(_lib.spmd_set_spin_limit(int(polls)), "spmd_set_spin_limit")
 
 
 from . import ops  # noqa: E402,F401  (tensor-level helpers)

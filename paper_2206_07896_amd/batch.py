@@ -104,8 +104,9 @@ class Batch:
         for i, (b, it, bpf) in enumerate(schedules):
             sch[i] = Schedule(int(b), int(it), int(bpf))
         size = int(_lib.spmd_batch_workspace_size_dep(arr, sch, dep_arr, n))
-        if size == 0:
-            raise SpmdError(-2, "spmd_batch_workspace_size (invalid items, schedules or dependencies)")
+        if size == 0:  # the plan is invalid: create reports why before it looks at the workspace
+            rc = _lib.spmd_batch_create_dep(arr, sch, dep_arr, n, None, 0, workers_per_cu, ctypes.byref(_P()))
+            raise SpmdError(rc if rc else -2, "spmd_batch_create (invalid items, schedules or dependencies)")
         raw = torch.empty(size + 256, dtype=torch.uint8, device=device or "cuda")
         off = (-raw.data_ptr()) % 256
         self.workspace = raw[off:off + size]
@@ -243,8 +244,9 @@ def launch_batch(launches, mode: int = SCHED_AS_LAUNCHED, workspace=None, stream
     synchronised)."""
     d = _Descs(launches)
     size = int(_lib.spmd_launch_batch_workspace_size(d.arr, d.n))
-    if size == 0:
-        raise SpmdError(-2, "spmd_launch_batch_workspace_size (a launch cannot be batched)")
+    if size == 0:  # a launch cannot be batched: the call reports why before it looks at the workspace
+        rc = _lib.spmd_launch_batch(d.arr, d.n, int(mode), None, 0, _stream_handle(stream))
+        raise SpmdError(rc if rc else -2, "spmd_launch_batch (a launch cannot be batched)")
     if workspace is None or workspace.numel() < size + 256:
         workspace = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
     off = (-workspace.data_ptr()) % 256

@@ -23,17 +23,20 @@
 // tiles fetched earlier).  A persistent workgroup takes a chunk with one
 // relaxed atomic add on a cursor and requests the next chunk as soon as it
 // starts the current one, so the atomic's round trip overlaps the block
-// bodies.  A SCAN segment has one cursor.  Every other segment cuts its
-// chunks into up to 8 contiguous ranges with a cursor each (ChunkRanges
-// below): a range's chunks run on one XCD and its draws do not queue
-// behind the other ranges'.  A workgroup exits once every cursor it draws
-// from has passed the end of its range, so every workgroup ends after
+// bodies (a SCAN worker draws once its tile has published its inclusive
+// prefix instead).  A segment cuts its chunks into up to 8 contiguous
+// ranges with a cursor each (ChunkRanges below): a range's chunks run on
+// one XCD and its draws do not queue behind the other ranges'.  A SCAN
+// segment is cut only at instance starts and only when its tiles are small;
+// otherwise it keeps one cursor.  A workgroup exits once every cursor it
+// draws from has passed the end of its range, so every workgroup ends after
 // finitely many fetches.
 #include <string.h>
 
 #include <algorithm>
 #include <mutex>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "cls_hist.hpp"
@@ -127,7 +130,7 @@ __device__ __forceinline__ void run_logical_block(const BatchDesc& d, uint32_t b
         uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
         uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + REDUCE_CTL_BYTES);
         reduce_block<B>(reinterpret_cast<const int32_t*>(d.in), nullptr, reinterpret_cast<int32_t*>(d.out), d.n,
-                        d.aux, d.nblocks, b, ctl, status, 0u, err, d.vec != 0u, L.r);
+                        d.aux, d.nblocks, b, ctl, status, err, d.vec != 0u, L.r);
     } else if constexpr (CLS == SPMD_SCAN_I32) {
         const int32_t* x = reinterpret_cast<const int32_t*>(d.in);
         int32_t* y = reinterpret_cast<int32_t*>(d.out);
@@ -244,7 +247,7 @@ __device__ __forceinline__ void run_fused_chunk(const BatchDesc& d, uint32_t q, 
         uint32_t* ctl = reinterpret_cast<uint32_t*>(d.ws);
         uint64_t* status = reinterpret_cast<uint64_t*>(d.ws + REDUCE_CTL_BYTES);
         reduce_block<B>(reinterpret_cast<const int32_t*>(d.in), nullptr, reinterpret_cast<int32_t*>(d.out), d.n,
-                        seg, nchunks, q, ctl, status, 0u, err, d.vec != 0u, L.r);
+                        seg, nchunks, q, ctl, status, err, d.vec != 0u, L.r);
         (void)lo;
         (void)hi;
     } else {
@@ -497,7 +500,7 @@ __global__ __launch_bounds__(B) void batch_persistent_kernel(const BatchDesc* __
     }
 }
 
-// Clears the run area (16-byte words) and the histogram outputs.
+// Clears the run area (16-byte words) and the histogram outputs of level 0.
 __global__ __launch_bounds__(256) void batch_prologue_kernel(u32x4* run, uint64_t run_words,
                                                              uint32_t* const* hist_out, uint32_t nhist) {
     if (blockIdx.x < nhist) {
@@ -507,6 +510,14 @@ __global__ __launch_bounds__(256) void batch_prologue_kernel(u32x4* run, uint64_
     const uint64_t stride = (uint64_t)(gridDim.x - nhist) * 256u;
     const u32x4 z = {0u, 0u, 0u, 0u};
     for (uint64_t i = (uint64_t)(blockIdx.x - nhist) * 256u + threadIdx.x; i < run_words; i += stride) run[i] = z;
+}
+
+// Clears the histogram outputs of one dependency level above 0, in stream
+// order just before that level: an instance of a lower level may still read
+// those bins (a histogram's bins are overwritten at its own level, as by a
+// run of the instances one by one in level order).
+__global__ __launch_bounds__(256) void batch_hist_clear_kernel(uint32_t* const* hist_out) {
+    hist_out[blockIdx.x][threadIdx.x] = 0u;
 }
 
 }  // namespace spmd
@@ -548,6 +559,9 @@ struct spmd_batch {
     std::vector<size_t> each_ws;        // per instance: offset of its standalone workspace
     std::vector<size_t> each_partials;  // per instance (REDUCE): offset of its partials
     uint32_t nhist = 0;
+    // queued HIST outputs in the list at hist_off, by level: level l owns
+    // entries [hist_lo[l], hist_lo[l + 1])
+    std::vector<uint32_t> hist_lo;
     uint64_t total_blocks = 0, total_chunks = 0;
     uint32_t each_launches = 0;
     const DevInfo* dev = nullptr;
@@ -618,6 +632,28 @@ uint64_t item_blocks(const spmd_batch_item& it, const spmd_schedule& s) {
     }
 }
 
+}  // namespace
+
+// Does an instance's output overlap its input?  Every class reads its whole
+// input before or while it writes, and a batch may run an instance more than
+// once (graph replays, the timing of the learned schedule's fallback), so an
+// output over the input would be read back as input: SPMD_ERR_ARGS.
+namespace spmd {
+bool batch_out_overlaps_in(const spmd_batch_item& it) {
+    uint64_t in_bytes = 4ull * it.n, out_bytes = 4;
+    switch (it.kernel_id) {
+    case SPMD_REDUCE_I32: out_bytes = 4; break;
+    case SPMD_SCAN_I32: out_bytes = 4ull * it.n; break;
+    case SPMD_HIST256_U32: out_bytes = 1024; break;
+    case SPMD_JACOBI5_F32: in_bytes = out_bytes = 4ull * it.n * it.ny; break;
+    }
+    if (!it.in) return false;
+    return overlap(it.in, in_bytes, it.out, out_bytes);
+}
+}  // namespace spmd
+
+namespace {
+
 // Run-area scratch of an instance under the queue.
 size_t run_scratch(const spmd_batch_item& it, uint64_t nb) {
     if (it.kernel_id == SPMD_REDUCE_I32) return align_up(REDUCE_CTL_BYTES + 8 * nb, 256);
@@ -679,12 +715,12 @@ int plan_layout(const spmd_batch_item* items, const spmd_schedule* sched, const 
         if (nb == 0) return SPMD_ERR_INVALID_DIM;
         if (nb >= (1ull << 31)) return SPMD_ERR_INVALID_DIM;
         if (!it.out || (!it.in && it.n)) return SPMD_ERR_ARGS;
-        if (it.kernel_id == SPMD_JACOBI5_F32 && it.in == it.out) return SPMD_ERR_ARGS;
+        if (batch_out_overlaps_in(it)) return SPMD_ERR_ARGS;
         blocks[i] = nb;
         run += run_scratch(it, nb);
         each += each_scratch(it, nb);
         key[i] = SegKey{L.level[i], group_of(it.kernel_id, s.block, s.items), is_direct(s) ? i : -1};
-        if (it.kernel_id == SPMD_HIST256_U32) ++nhist;
+        if (it.kernel_id == SPMD_HIST256_U32 && !is_direct(s)) ++nhist;
     }
     // segments in (level, group, queue first) order
     std::vector<SegKey> keys(key);
@@ -846,9 +882,9 @@ int enqueue_run(spmd_batch* b, hipStream_t s) {
     clear_stale_error();
     const uint64_t run_words = b->run_bytes / 16;
     const uint32_t zero_blocks = (uint32_t)std::min<uint64_t>(1024, std::max<uint64_t>(1, cdiv(run_words, 256)));
-    hipLaunchKernelGGL(batch_prologue_kernel, dim3(b->nhist + zero_blocks), dim3(256), 0, s,
-                       reinterpret_cast<u32x4*>(b->ws), run_words,
-                       reinterpret_cast<uint32_t* const*>(b->ws + b->hist_off), b->nhist);
+    uint32_t* const* hist_list = reinterpret_cast<uint32_t* const*>(b->ws + b->hist_off);
+    hipLaunchKernelGGL(batch_prologue_kernel, dim3(b->hist_lo[1] + zero_blocks), dim3(256), 0, s,
+                       reinterpret_cast<u32x4*>(b->ws), run_words, hist_list, b->hist_lo[1]);
     const BatchDesc* descs = reinterpret_cast<const BatchDesc*>(b->ws + b->desc_off);
     uint32_t* err = b->dev->err_word;
     hipError_t e = hipGetLastError();
@@ -859,6 +895,11 @@ int enqueue_run(spmd_batch* b, hipStream_t s) {
         size_t hi = lo;
         while (hi < nseg && b->seg[hi].level == b->seg[lo].level) ++hi;
         const uint32_t lev = b->seg[lo].level;
+        if (lev > 0 && b->hist_lo[lev + 1] > b->hist_lo[lev]) {
+            hipLaunchKernelGGL(batch_hist_clear_kernel, dim3(b->hist_lo[lev + 1] - b->hist_lo[lev]), dim3(256), 0, s,
+                               hist_list + b->hist_lo[lev]);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+        }
         const bool fork = hi - lo >= 2 && lev < b->ev_fork.size() && b->ev_fork[lev] != nullptr;
         if (fork) {
             int rc = side ? SPMD_OK : side_streams(b->dev, &side);
@@ -956,7 +997,7 @@ int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sch
     std::vector<BatchDesc> descs(n);
     std::vector<std::vector<uint32_t>> cmap(nseg);
     for (size_t k = 0; k < nseg; ++k) cmap[k].reserve(b->seg[k].chunks);
-    std::vector<uint64_t> hist_ptrs;
+    std::vector<std::pair<uint32_t, uint64_t>> hist_lv;  // (level, bins) of queued HIST instances
     size_t run = L.cursor_bytes, each = L.each_off;
     b->each_ws.assign(n, 0);
     b->each_partials.assign(n, 0);
@@ -984,7 +1025,8 @@ int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sch
         case SPMD_SCAN_I32: d.vec = va && vb; break;
         case SPMD_JACOBI5_F32: d.aux = (uint32_t)cdiv(it.n, 64); break;
         }
-        if (it.kernel_id == SPMD_HIST256_U32) hist_ptrs.push_back((uint64_t)(uintptr_t)it.out);
+        if (it.kernel_id == SPMD_HIST256_U32 && !is_direct(s))  // own grids clear their bins themselves
+            hist_lv.emplace_back(L.level[i], (uint64_t)(uintptr_t)it.out);
         const uint64_t nch = is_direct(s) ? 0 : cdiv(blocks[i], d.bpf);
         for (uint64_t k = 0; k < nch; ++k) cm.push_back((uint32_t)i);
         run += run_scratch(it, blocks[i]);
@@ -998,6 +1040,16 @@ int spmd_batch_create_dep(const spmd_batch_item* items, const spmd_schedule* sch
         b->total_blocks += blocks[i];
         b->each_launches += it.kernel_id == SPMD_HIST256_U32 ? 2u : 1u;
     }
+    std::stable_sort(hist_lv.begin(), hist_lv.end(),
+                     [](const auto& a, const auto& c) { return a.first < c.first; });
+    const uint32_t nlev = b->seg.back().level + 1;
+    std::vector<uint64_t> hist_ptrs(hist_lv.size());
+    b->hist_lo.assign(nlev + 1, 0);
+    for (size_t k = 0; k < hist_lv.size(); ++k) {
+        hist_ptrs[k] = hist_lv[k].second;
+        ++b->hist_lo[hist_lv[k].first + 1];
+    }
+    for (uint32_t l = 0; l < nlev; ++l) b->hist_lo[l + 1] += b->hist_lo[l];
     hipError_t e = hipMemcpy(b->ws + L.desc_off, descs.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess && !hist_ptrs.empty())
         e = hipMemcpy(b->ws + L.hist_off, hist_ptrs.data(), 8 * hist_ptrs.size(), hipMemcpyHostToDevice);

@@ -20,6 +20,7 @@ template <int B>
 struct ReduceLds {
     uint32_t wave[B / 64];
     uint32_t last;
+    uint32_t epoch;
 };
 
 // Sum of v over the block; valid in thread 0 only.  Ends with a barrier so
@@ -84,10 +85,12 @@ __device__ __forceinline__ uint32_t segment_sum(const int32_t* __restrict__ x, u
     return acc;
 }
 
-constexpr uint32_t REDUCE_SPIN_LIMIT = 1u << 22;
 constexpr uint32_t REDUCE_SUBTICKETS = 64;   // first-level ticket counters
 constexpr uint32_t REDUCE_TICKET_STRIDE = 32;  // u32 words between counters (128 B)
 constexpr size_t REDUCE_CTL_BYTES = (REDUCE_SUBTICKETS + 1) * REDUCE_TICKET_STRIDE * 4;
+// The launch epoch: in the top counter's line, 64 bytes past the counter.
+// It tags the launch's status words, and the finishing block advances it.
+constexpr uint32_t REDUCE_EPOCH_WORD = 16;
 
 // Two-level completion ticket.  Counters on one address serialise at the
 // device coherence point, so block b counts on sub-counter b % 64 (each on
@@ -107,32 +110,37 @@ __device__ __forceinline__ bool reduce_ticket_last(uint32_t* ctl, uint32_t G, ui
 }
 
 // One logical block `bid` of a G-block reduction.  Cross-block state
-// (`ctl`, `status`): `ctl` holds the two-level completion ticket
-// (REDUCE_CTL_BYTES), status[b] the partial of block b as a tagged status
-// word.  Thread 0 publishes the block's partial (to `partials`, when given,
-// and as a status word), then takes a ticket; the last block reads the G
-// status words (waiting, boundedly, for any not yet visible), sums them,
-// writes *out and clears the status words, so the next launch finds the
-// state as the first one did.  Returns true in the block that finished.
+// (`ctl`, `status`): `ctl` holds the two-level completion ticket and the
+// launch epoch (REDUCE_CTL_BYTES), status[b] the partial of block b as a
+// status word tagged with the epoch.  Thread 0 publishes the block's
+// partial (to `partials`, when given, and as a status word), then takes a
+// ticket; the last block reads the G status words (waiting, boundedly, for
+// any not yet visible), sums them, writes *out and advances the epoch, so
+// words of this launch -- even one stored late, after a wait gave up --
+// read as unwritten in the next.  Returns true in the block that finished.
 template <int B>
 __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int32_t* partials, int32_t* out,
                                              uint32_t n, uint32_t seg, uint32_t G, uint32_t bid, uint32_t* ctl,
-                                             uint64_t* status, uint32_t tag, uint32_t* err, bool vec,
-                                             ReduceLds<B>& L) {
+                                             uint64_t* status, uint32_t* err, bool vec, ReduceLds<B>& L) {
     const uint64_t lo = (uint64_t)bid * seg;
     const uint64_t hi = lo + seg < (uint64_t)n ? lo + seg : (uint64_t)n;
+    // the epoch's round trip overlaps the segment's loads
+    const uint32_t epoch = threadIdx.x == 0 ? load_dev(ctl + REDUCE_EPOCH_WORD) : 0u;
     const uint32_t tot = block_sum_t0<B>(segment_sum<B>(x, lo, hi, vec, bid), L);
     if (threadIdx.x == 0) {
         if (partials) partials[bid] = (int32_t)tot;
-        status_put(status + bid, status_pack(tot, 1u, tag));
+        status_put(status + bid, status_pack(tot, 1u, epoch));
         L.last = reduce_ticket_last(ctl, G, bid) ? 1u : 0u;
+        L.epoch = epoch;
     }
     __syncthreads();
     const bool last = L.last != 0u;
+    const uint32_t tag = L.epoch;
     __syncthreads();
     if (!last) return false;
     // The G status words, eight independent loads in flight per thread;
     // only words not yet visible are polled again.
+    const uint32_t limit = spin_limit(err);
     uint32_t acc = 0;
     for (uint32_t j0 = threadIdx.x; j0 < G; j0 += 8u * B) {
         uint64_t w[8];
@@ -145,7 +153,7 @@ __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int3
         for (int q = 0; q < 8; ++q) {
             const uint32_t j = j0 + (uint32_t)q * B;
             for (uint32_t spins = 0; status_flag(w[q], tag) == 0u; ++spins) {
-                if (spins >= REDUCE_SPIN_LIMIT) {
+                if (spins >= limit) {
                     atomicOr(err, ERRBIT_SPIN_LIMIT);
                     w[q] = 0;
                     break;
@@ -157,10 +165,10 @@ __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int3
         }
     }
     const uint32_t total = block_sum_t0<B>(acc, L);
-    // Every other block has published and returned: clear the status words
-    // for the next launch.
-    for (uint32_t j = threadIdx.x; j < G; j += B) status_put(status + j, 0ull);
-    if (threadIdx.x == 0) *out = (int32_t)total;
+    if (threadIdx.x == 0) {
+        *out = (int32_t)total;
+        put_dev(ctl + REDUCE_EPOCH_WORD, tag + 1u);  // every block of this launch has read the epoch
+    }
     return true;
 }
 

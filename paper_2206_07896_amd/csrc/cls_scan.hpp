@@ -35,7 +35,6 @@
 namespace spmd {
 
 constexpr uint32_t SCAN_AGG = 1u, SCAN_INCL = 2u;
-constexpr uint32_t LOOKBACK_SPIN_LIMIT = 1u << 22;
 
 template <int B, int I>
 struct ScanLds {
@@ -67,9 +66,10 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
         return 0;
     }
     if (lane == 0) status_put(status + tile, status_pack(agg, SCAN_AGG, tag));
+    const uint32_t limit = spin_limit(err);
     uint32_t spins = 0, nap = 1;
     while (status_flag(status_get(status + tile - 1), tag) == 0u) {
-        if (++spins >= LOOKBACK_SPIN_LIMIT) break;  // the window loop below reports it
+        if (++spins >= limit) break;  // the window loop below reports it
         backoff_sleep(nap);
         nap = nap < 16u ? nap * 2u : 16u;
     }
@@ -112,7 +112,7 @@ __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t til
                 if (__builtin_amdgcn_ballot_w64(nearer && flg[j] == 0u)) missing = true;
             }
             if (!missing) break;
-            if (++spins >= LOOKBACK_SPIN_LIMIT) {
+            if (++spins >= limit) {
                 if (lane == 0) atomicOr(err, ERRBIT_SPIN_LIMIT);
 #pragma unroll
                 for (int j = 0; j < LOOKBACK_PER_LANE; ++j)

@@ -24,11 +24,19 @@ enum : uint32_t {
 constexpr size_t BATCH_CURSOR_RANGES = 8, BATCH_CURSOR_SLOT = 128;
 constexpr size_t BATCH_SEG_CURSOR_BYTES = BATCH_CURSOR_RANGES * BATCH_CURSOR_SLOT;
 
+// A device's error state, two words: [0] the error bits above, [1] the
+// bound on every cross-block wait, in polls (0: DEFAULT_SPIN_LIMIT).
+constexpr uint32_t DEFAULT_SPIN_LIMIT = 1u << 22;
+__device__ __forceinline__ uint32_t spin_limit(const uint32_t* err) {
+    const uint32_t v = err[1];
+    return v ? v : DEFAULT_SPIN_LIMIT;
+}
+
 struct DevInfo {
     int device;
     int num_cus;
     size_t max_shmem_per_block;
-    uint32_t* err_word;  // device address of this device's error word
+    uint32_t* err_word;  // device address of this device's error state (two words)
 };
 
 struct LaunchCtx {
@@ -53,6 +61,11 @@ inline uint32_t next_pow2(uint32_t v) {
     return p;
 }
 inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+// Do the byte ranges [a, a + na) and [b, b + nb) share a byte?
+inline bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+}
 
 // Segment of a block in the reduce and histogram classes: S = 4*ceil(n/(4G)).
 // Elements per block, a multiple of 4: 4 * ceil(n / (4 * grid)).  It fits

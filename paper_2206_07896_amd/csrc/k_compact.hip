@@ -92,6 +92,7 @@ int launch_compact_i32(const LaunchCtx& c) {
     auto t = (int32_t)arg<uint32_t>(c.args, 4);
     auto ws = arg<uint32_t*>(c.args, 5);
     if (!cnt || (n && (!x || !y))) return SPMD_ERR_ARGS;
+    if (overlap(x, 4ull * n, y, 4ull * n) || overlap(x, 4ull * n, cnt, 4)) return SPMD_ERR_ARGS;
     if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
     const uint64_t per = ((uint64_t)n + (uint64_t)c.grid.x * B - 1) / ((uint64_t)c.grid.x * B);
     const uint32_t I = next_pow2(per ? (uint32_t)per : 1u);

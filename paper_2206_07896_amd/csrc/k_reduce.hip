@@ -1,9 +1,9 @@
 // k_reduce.hip -- REDUCE_I32 kernel and launcher.
 //
-// Workspace: the two-level completion ticket (REDUCE_CTL_BYTES, counters
-// on separate cache lines), then one u64 status word per block (tag 0: the
-// finishing block clears them, so every launch starts from the zero-filled
-// state).
+// Workspace: the two-level completion ticket and the launch epoch
+// (REDUCE_CTL_BYTES, counters on separate cache lines), then one u64 status
+// word per block, tagged with the epoch: the finishing block re-arms the
+// ticket and advances the epoch, so the next launch needs no clearing.
 #include "cls_reduce.hpp"
 #include "common.hpp"
 
@@ -17,7 +17,7 @@ __global__ __launch_bounds__(B) void reduce_i32_kernel(const int32_t* __restrict
                                                         uint32_t* err, bool vec) {
     __shared__ ReduceLds<B> L;
     uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + REDUCE_WS_HEADER);
-    reduce_block<B>(x, partials, out, n, seg, gridDim.x, blockIdx.x, ws, status, 0u, err, vec, L);
+    reduce_block<B>(x, partials, out, n, seg, gridDim.x, blockIdx.x, ws, status, err, vec, L);
 }
 
 size_t ws_reduce_i32(spmd_dim3 grid, spmd_dim3, uint64_t) { return REDUCE_WS_HEADER + 8ull * grid.x; }

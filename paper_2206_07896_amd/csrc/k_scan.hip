@@ -96,6 +96,7 @@ int launch_scan_i32(const LaunchCtx& c) {
     auto n = arg<uint32_t>(c.args, 2);
     auto ws = arg<uint32_t*>(c.args, 3);
     if (n && (!x || !y)) return SPMD_ERR_ARGS;
+    if (overlap(x, 4ull * n, y, 4ull * n)) return SPMD_ERR_ARGS;
     if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
     const uint64_t per = ((uint64_t)n + (uint64_t)c.grid.x * B - 1) / ((uint64_t)c.grid.x * B);
     const uint32_t I = next_pow2(per ? (uint32_t)per : 1u);

@@ -19,6 +19,12 @@
 
 using namespace spmd;
 
+namespace spmd {
+// A batch instance whose output overlaps its input (batch.hip; refused with
+// SPMD_ERR_ARGS).
+bool batch_out_overlaps_in(const spmd_batch_item& it);
+}  // namespace spmd
+
 namespace {
 
 constexpr uint32_t CAND_BLOCKS[4] = {64, 128, 256, 512};
@@ -258,8 +264,10 @@ int spmd_launch_batch(const spmd_launch_desc* descs, int n, int mode, void* work
     if (!descs || n <= 0 || (mode != SPMD_SCHED_AS_LAUNCHED && mode != SPMD_SCHED_LEARNED)) return SPMD_ERR_ARGS;
     std::vector<spmd_batch_item> items(n);
     int rc;
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if ((rc = to_item(descs[i], &items[i]))) return rc;
+        if (batch_out_overlaps_in(items[i])) return SPMD_ERR_ARGS;
+    }
     const size_t bound = batch_bound(items);
     if (!bound) return SPMD_ERR_INVALID_DIM;
     const InferLayout IL = infer_layout((size_t)n);

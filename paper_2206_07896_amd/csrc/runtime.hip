@@ -18,9 +18,11 @@
 
 namespace spmd {
 
-// One error word per device.  Host code never uses this name as an address:
-// the address comes from hipGetSymbolAddress with the device current.
-__device__ uint32_t g_error_word;
+// One error state per device: the error word, then the spin limit of
+// cross-block waits (common.hpp).  Host code never uses this name as an
+// address: the address comes from hipGetSymbolAddress with the device
+// current.
+__device__ uint32_t g_error_word[2];
 
 namespace {
 
@@ -81,7 +83,7 @@ int runtime_dev(const DevInfo** out) {
         void* p = nullptr;
         if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_error_word))) != hipSuccess) return hip_fail(e);
         di.err_word = static_cast<uint32_t*>(p);
-        if ((e = hipMemset(di.err_word, 0, sizeof(uint32_t))) != hipSuccess) return hip_fail(e);
+        if ((e = hipMemset(di.err_word, 0, 2 * sizeof(uint32_t))) != hipSuccess) return hip_fail(e);
         g_dev_ready[d] = true;
     }
     *out = &g_dev[d];
@@ -154,6 +156,14 @@ int spmd_sync_timeout(void* stream, uint32_t ms) {
         std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
     return read_and_clear_error(di);
+}
+
+int spmd_set_spin_limit(uint32_t polls) {
+    const DevInfo* di = nullptr;
+    int rc = runtime_dev(&di);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(di->err_word + 1, &polls, sizeof polls, hipMemcpyHostToDevice);
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }
 
 const char* spmd_kernel_signature(int kernel_id) {

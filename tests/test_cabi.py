@@ -127,7 +127,7 @@ def _items(spmd, specs):
     arr = (B.BatchItem * len(specs))()
     sch = (B.Schedule * len(specs))()
     for i, (kid, n, ny, s) in enumerate(specs):
-        arr[i] = B.BatchItem(kid, n, ny, 64, 0x1000, 0x2000)
+        arr[i] = B.BatchItem(kid, n, ny, 64, (1 << 32) + (i << 28), (1 << 36) + (i << 28))  # disjoint buffers
         sch[i] = B.Schedule(*s)
     return arr, sch
 
@@ -218,8 +218,9 @@ def test_launch_batch_rejects_unbatchable_launches(spmd):
                             C.cast(arr, C.POINTER(C.c_void_p))), arr
 
     n = C.c_uint32(1000)
-    p = C.c_void_p(0x1000)
-    ptrs = [C.cast(C.pointer(p), C.c_void_p).value] * 3 + [C.cast(C.pointer(n), C.c_void_p).value]
+    p, q = C.c_void_p(0x100000), C.c_void_p(0x200000)  # keys, bins: disjoint
+    ptrs = [C.cast(C.pointer(p), C.c_void_p).value, C.cast(C.pointer(q), C.c_void_p).value,
+            C.cast(C.pointer(q), C.c_void_p).value, C.cast(C.pointer(n), C.c_void_p).value]
     ok, keep = desc(spmd.HIST256_U32, (4, 1, 1), (256, 1, 1), ptrs[:2] + [ptrs[3]])
     lib = spmd.lib()
     one = (B.LaunchDesc * 1)(ok)
@@ -251,7 +252,7 @@ def test_launch_batch_workspace_covers_every_schedule(spmd):
         kid = [spmd.REDUCE_I32, spmd.SCAN_I32, spmd.HIST256_U32, spmd.JACOBI5_F32][i % 4]
         n = int(rng.integers(1, 1 << 20))
         bd = int(rng.choice([32, 64, 96, 128, 256, 512, 1024]))
-        vals = [C.c_void_p(0x10000 * (i + 1)), C.c_void_p(0x10000 * (i + 1) + 0x8000)]
+        vals = [C.c_void_p((i + 1) << 32), C.c_void_p(((i + 1) << 32) + (1 << 28))]  # input, output: disjoint
         if kid == spmd.JACOBI5_F32:
             nx = ny = max(1, int(np.sqrt(n)))
             ints = [C.c_uint32(nx), C.c_uint32(ny)]
@@ -341,3 +342,28 @@ def test_sched_chunks_closed_forms(spmd):
         else:
             nbj = -(-300 // 64) * -(-200 // ((blk // 64) * it))  # 64-column blocks of blk/64 rows x it cells
             assert ch[2, j] == -(-nbj // bpf)
+
+
+def test_batch_rejects_output_over_input(spmd):
+    """An instance's output may not overlap its input (the plan may run it
+    more than once): refused on the host for every batchable class, while
+    adjacent buffers are accepted."""
+    from paper_2206_07896_amd import batch as B
+
+    lib = spmd.lib()
+    base = 0x100000
+
+    def ok(kid, n, ny, inp, out):
+        items = (B.BatchItem * 1)(B.BatchItem(kid, n, ny, 256, inp, out))
+        sch = (B.Schedule * 1)(B.Schedule(256, 4, 1))
+        return lib.spmd_batch_workspace_size(items, sch, 1) > 0
+
+    n = 1000
+    for kid, ny, out_bytes in ((spmd.SCAN_I32, 1, 4 * n), (spmd.REDUCE_I32, 1, 4), (spmd.HIST256_U32, 1, 1024),
+                               (spmd.JACOBI5_F32, 20, 4 * n * 20)):
+        in_bytes = 4 * n * ny
+        assert not ok(kid, n, ny, base, base), kid                            # in place
+        assert not ok(kid, n, ny, base, base + in_bytes - 4), kid             # output starts inside the input
+        assert not ok(kid, n, ny, base + out_bytes - 4, base), kid            # input starts inside the output
+        assert ok(kid, n, ny, base, base + in_bytes), kid                     # adjacent after
+        assert ok(kid, n, ny, base + out_bytes, base), kid                    # adjacent before

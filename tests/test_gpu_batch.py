@@ -445,3 +445,160 @@ def test_dependency_across_queues(spmd):
         assert np.array_equal(host(h).view(np.uint32), want_h), mode
         assert int(host(r)[0]) == want_r, mode
     b.close()
+
+
+def _launch_desc(spmd, W, data, i):
+    """Instance i of a mixed workload as the CUDA launch it stands for: its
+    blockDim, 4 elements per thread (JACOBI: 64-wide blocks, 4 cells down a
+    column), the packed arguments of spmd_launch."""
+    s = data.specs[i]
+    k, bd = s["kid"], s["block_dim"]
+    x, y = data.input_of(i), data.output_of(i)
+    if k == spmd.JACOBI5_F32:
+        by = bd // 64
+        grid = (-(-s["nx"] // 64), -(-s["ny"] // (by * 4)))
+        return (k, grid, (64, by), 0, [x, y, s["nx"], s["ny"]])
+    grid = (max(1, -(-s["n"] // (bd * 4))),)
+    if k == spmd.REDUCE_I32:
+        return (k, grid, (bd,), 4 * bd, [x, y, y, s["n"], y])  # the batch writes `out` only
+    if k == spmd.SCAN_I32:
+        return (k, grid, (bd,), 0, [x, y, s["n"], y])           # workspace unused in a batch
+    return (k, grid, (bd,), 0, [x, y, s["n"]])
+
+
+def _oracle_of(W, data, i):
+    s = data.specs[i]
+    x = data.host_input(i)
+    k = W.KIND_NAMES[s["kid"]]
+    if k == "reduce":
+        return np.array([oracle.reduce_i32(x, 1, 64)[1]], np.int32)
+    if k == "scan":
+        return oracle.scan_i32(x, 64, 4)
+    if k == "hist":
+        return oracle.hist256_u32(x, 1, 64).view(np.int32)
+    return oracle.jacobi5_f32(x, 16, 16)
+
+
+@pytest.mark.timeout(900)
+def test_mixed_workload_configured_size(spmd):
+    """The measured mixed workload at its configured size: 10 000 launches,
+    class uniform over the four batchable classes, n = round(2^U) with
+    U ~ U[10, 22] (about 5e9 elements), blockDim uniform over 64..512, run
+    by spmd_launch_batch under SPMD_SCHED_LEARNED with the shipped cost
+    model and its fallback threshold (low-confidence launches are tuned
+    exhaustively first).  Every instance with n <= 2^14 and a seeded sample
+    of 200 larger ones are compared with the oracle; the whole output arena
+    must then equal, byte for byte, the batch-aware learned plan that the
+    measurement replays from a graph (model choice without fallback) and
+    the one-launch-per-instance baseline."""
+    import torch
+
+    from paper_2206_07896_amd import learned as L
+    from paper_2206_07896_amd import workload as W
+
+    model = L.load_default()
+    assert model is not None, "the package ships a cost model"
+    specs = W.mixed_specs(10000)
+    data = W.MixedData(specs)
+    launches = [_launch_desc(spmd, W, data, i) for i in range(len(specs))]
+    say("mixed workload 10000 launches, SCHED_LEARNED, tau", model.tau)
+    spmd.batch.model_load(model.params, model.norm, model.tau)
+    try:
+        data.outputs.fill_(-1)
+        ws = spmd.batch.launch_batch(launches, spmd.batch.SCHED_LEARNED)
+        spmd.sync()
+        rep = spmd.batch.launch_batch_report()
+        del ws
+    finally:
+        spmd.batch.model_load(model.params[:0], model.norm, 0.0)  # unload
+    say("report", rep)
+    assert rep["launches"] == 10000 and rep["by_model"] + rep["tuned"] + rep["cached"] == 10000
+    assert rep["by_model"] > 0
+    got_all = data.outputs.clone()
+    small = [i for i, s in enumerate(specs) if s["n"] <= 1 << 14]
+    large = [i for i, s in enumerate(specs) if s["n"] > 1 << 14]
+    rng = np.random.default_rng(0xC4)
+    sample = sorted(rng.choice(large, 200, replace=False).tolist())
+    say("oracle checks", len(small), "small +", len(sample), "large")
+    assert len(small) > 2500
+    for i in small + sample:
+        want = _oracle_of(W, data, i)
+        g = data.output_of(i).cpu().numpy()
+        assert np.array_equal(g, want.reshape(g.shape)), (i, specs[i]["kid"], specs[i]["n"])
+    # the measured plan (batch-aware learned choice, graph replay) and the baseline
+    choice, _, _ = model.choose(specs, slack=L.BATCH_SLACK)
+    b = spmd.batch.Batch(data.items(), [L.CANDIDATES[j] for j in choice])
+    for mode in ("graph", "graph", "each"):
+        say("mixed workload 10000", mode)
+        data.outputs.fill_(-1)
+        b.graph_launch() if mode == "graph" else b.launch_each()
+        spmd.sync()
+        assert bool(torch.equal(data.outputs, got_all)), mode
+    b.close()
+    del data
+    torch.cuda.empty_cache()
+
+
+def test_hist_bins_cleared_at_their_own_level(spmd):
+    """One 256-bin buffer read and rewritten across dependency levels: scan
+    of its prior contents (level 0), histogram of keys A into it (1), scan
+    of those counts (2), histogram of keys B into it (3).  Each histogram
+    overwrites the bins at its own level, so the first scan sees the prior
+    contents and the buffer ends as the counts of B alone."""
+    import torch
+
+    say("hist bins across levels")
+    prior = synth.uniform_int32(0xB1, 256, -1000, 1000)
+    ka = synth.zipf_u32(0xB2, 50001)
+    kb = synth.zipf_u32(0xB3, 70003) ^ (synth.uniform_u32(0xB4, 70003) & np.uint32(0xFFFFFF00))
+    h = dev(prior)
+    s1 = torch.empty(256, dtype=torch.int32, device="cuda")
+    s2 = torch.empty(256, dtype=torch.int32, device="cuda")
+    ta, tb = dev(ka), dev(kb)
+    items = [(spmd.SCAN_I32, 256, 1, 64, h, s1), (spmd.HIST256_U32, ka.size, 1, 256, ta, h),
+             (spmd.SCAN_I32, 256, 1, 128, h, s2), (spmd.HIST256_U32, kb.size, 1, 512, tb, h)]
+    cnt_a = oracle.hist256_u32(ka, 1, 64)
+    want_s1 = oracle.scan_i32(prior, 64, 4)
+    want_s2 = oracle.scan_i32(cnt_a.view(np.int32), 64, 4)
+    want_h = oracle.hist256_u32(kb, 1, 64)
+    for scheds in ([(64, 1, 1), (256, 4, 2), (128, 2, 1), (512, 8, 1)],     # every level through the queue
+                   [(64, 1, 1), (256, 4, 0), (128, 2, 1), (512, 8, 0)]):    # histograms as their own grids
+        b = spmd.batch.Batch(items, scheds, deps=[None, 0, 1, 2])
+        for mode in ("eager", "graph", "graph"):
+            h.copy_(torch.from_numpy(prior).cuda())
+            s1.fill_(0)
+            s2.fill_(0)
+            b.launch() if mode == "eager" else b.graph_launch()
+            spmd.sync()
+            assert np.array_equal(host(s1), want_s1), (scheds, mode)
+            assert np.array_equal(host(s2), want_s2), (scheds, mode)
+            assert np.array_equal(host(h).view(np.uint32), want_h), (scheds, mode)
+        b.close()
+
+
+def test_output_over_input_rejected(spmd):
+    """An in-place scan or compaction, and a batch instance whose output
+    overlaps its input, are refused before any work is enqueued (a batch may
+    run an instance several times: graph replays, the fallback's timing)."""
+    import torch
+
+    say("overlap rejected")
+    x = torch.arange(1000, dtype=torch.int32, device="cuda")
+    keep = x.clone()
+    ws = spmd.ops.workspace(spmd.SCAN_I32, 16, 64, 1000)
+    for y in (x, x[10:]):  # in place, and shifted by 10 elements
+        with pytest.raises(spmd.SpmdError) as e:
+            spmd.launch(spmd.SCAN_I32, 16, 64, 0, [x[: y.numel()], y, y.numel(), ws])
+        assert e.value.kind == "ARGS"
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(spmd.SpmdError) as e:
+        spmd.ops.compact_i32(x, 0, y=x, count=cnt)
+    assert e.value.kind == "ARGS"
+    with pytest.raises(spmd.SpmdError) as e:
+        spmd.batch.Batch([(spmd.SCAN_I32, 1000, 1, 256, x, x)], [(256, 4, 1)])
+    assert e.value.kind == "ARGS"
+    with pytest.raises(spmd.SpmdError) as e:
+        spmd.batch.launch_batch([(spmd.SCAN_I32, (4,), (256,), 0, [x, x, 1000, ws])], spmd.batch.SCHED_AS_LAUNCHED)
+    assert e.value.kind == "ARGS"
+    spmd.sync()
+    assert bool(torch.equal(x, keep))

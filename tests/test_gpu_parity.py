@@ -128,19 +128,34 @@ def test_scan(spmd, n, block, items):
         assert np.array_equal(got, want), (rep, int(np.argmax(got != want)))
 
 
-def test_scan_workload_size(spmd):
+@pytest.mark.parametrize("items", [16, 32, 64])
+def test_scan_workload_size(spmd, items):
+    """2^26 int32 U[0, 100] at blockDim 512 -- at 64 items the measured
+    step's launch (2048 tiles over the resident blocks, so every block loops
+    over several tiles), launched as the step does: twice on one workspace,
+    into two outputs.  Checked over all 2^26 elements by the complete
+    invariant (y[0] = x[0], y[i] - y[i-1] = x[i] mod 2^32) and against the
+    oracle on a 2^20 prefix."""
+    import torch
+
     n = 1 << 26
-    say("scan 2^26 block 512")
+    say("scan 2^26 block 512 items", items)
     x = synth.uniform_int32(synth.SEED_SCAN, n, 0, 100)
-    y = spmd.ops.scan_i32(dev(x), 512, 16)
+    xt = dev(x)
+    ws = spmd.ops.workspace(spmd.SCAN_I32, spmd.ops.scan_grid(n, 512, items), 512, n)
+    ys = [torch.empty_like(xt) for _ in range(2)]
+    for y in ys:
+        spmd.ops.scan_i32(xt, 512, items, y=y, ws=ws)
     spmd.sync()
-    got = host(y).view(np.uint32)
     xu = x.view(np.uint32)
-    assert got[0] == xu[0]
-    assert np.array_equal((got[1:] - got[:-1]).astype(np.uint32), xu[1:])
-    assert int(got[-1]) == int(x.astype(np.int64).sum()) % 2**32
-    m = 1 << 20  # a prefix of the scan is the scan of the prefix
-    assert np.array_equal(got[:m].view(np.int32), oracle.scan_i32(x[:m], 512, 16))
+    want_prefix = oracle.scan_i32(x[:1 << 20], 512, items)  # a prefix of the scan is the scan of the prefix
+    for rep, y in enumerate(ys):
+        got = host(y).view(np.uint32)
+        assert got[0] == xu[0], rep
+        bad = np.flatnonzero((got[1:] - got[:-1]).astype(np.uint32) != xu[1:])
+        assert bad.size == 0, (rep, bad[:5] + 1)
+        assert int(got[-1]) == int(x.astype(np.int64).sum()) % 2**32, rep
+        assert np.array_equal(got[:1 << 20].view(np.int32), want_prefix), rep
 
 
 # --------------------------------------------------------------------------
@@ -527,14 +542,28 @@ def test_compact_edges(spmd):
     assert int(count.item()) == 0
 
 
-def test_compact_workload_size(spmd):
-    say("compact 2^26, t = 0")
+@pytest.mark.parametrize("block,items", [(256, 16), (1024, 32), (512, 32)])
+def test_compact_workload_size(spmd, block, items):
+    """2^26 int32 U[-1000, 1000], t = 0, element by element against the
+    oracle -- at 1024 x 32 and 512 x 32 the measured launches, run as the
+    measurement does: twice on one workspace, with the input rotated over
+    two copies and one output reused."""
+    import torch
+
+    say("compact 2^26, t = 0", block, items)
     n = 1 << 26
     x = synth.uniform_int32(synth.SEED_SCAN, n, -1000, 1000)
-    y, count = spmd.ops.compact_i32(dev(x), 0, 256, 16)
-    spmd.sync()
+    xs = [dev(x), dev(x)]
+    ws = spmd.ops.workspace(spmd.COMPACT_I32, spmd.ops.compact_grid(n, block, items), block, n)
+    y = torch.full((n,), 7, dtype=torch.int32, device="cuda")
     want = oracle.compact_i32(x, 0)
-    m = int(count.item())
-    assert m == want.size
-    got = host(y)[:m]
-    assert np.array_equal(got, want)
+    for rep in range(2):
+        count = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        spmd.ops.compact_i32(xs[rep], 0, block, items, y=y, count=count, ws=ws)
+        spmd.sync()
+        m = int(count.item())
+        assert m == want.size, (rep, m)
+        got = host(y)
+        bad = np.flatnonzero(got[:m] != want)
+        assert bad.size == 0, (rep, bad[:5])
+        assert np.all(got[m:] == 7), rep  # untouched beyond the count
