@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--learned-eval", type=int, default=0, metavar="HELDOUT",
                     help="also tune, train and score the cost model on this many held-out launches "
                          "(500 training launches; minutes of GPU time)")
+    ap.add_argument("--regret-count", type=int, default=200,
+                    help="held-out launches timed under every schedule to score the shipped cost model (0: skip)")
     ap.add_argument("--only-step", action="store_true",
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
@@ -228,6 +230,17 @@ def main():
     if not args.no_mixed:
         mixed = mixed_queue(spmd, args.mixed_count)
 
+    regret = None
+    if args.regret_count and not args.no_mixed:
+        from paper_2206_07896_amd import learned as L
+
+        model = L.load_default()
+        if model is not None:
+            log(f"schedule regret: {args.regret_count} held-out launches x every schedule")
+            regret = L.heldout_regret(model, args.regret_count)
+            log(f"schedule regret: {json.dumps(regret)}")
+        torch.cuda.empty_cache()
+
     learned_eval = None
     if args.learned_eval:
         from paper_2206_07896_amd import learned as L
@@ -237,6 +250,14 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(xs_h, ks_h, step_bytes)
+        del xs_h, ks_h
+        extra_cpu = cpu_executor_baselines(args.mixed_count)
+        for key, rec in extra_cpu.items():
+            if key == "mixed_queue":
+                if mixed is not None:
+                    mixed["cpu_oracle"] = rec
+            else:
+                kernels.setdefault(key, {})["cpu_oracle"] = rec
 
     out = {
         "metric": "GB/s & % HBM peak per kernel; mixed-queue launches/s, persistent vs 1-by-1",
@@ -262,6 +283,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "mixed_queue": mixed,
+        "schedule_regret": regret,
     }
     if learned_eval is not None:
         out["learned_schedule_eval"] = learned_eval
@@ -423,7 +445,7 @@ def jacobi_workloads(spmd, synth):
 
         ms = measure(run, 3, warmup=1) / sweeps
         byt = 8 * nn * nn
-        res[f"jacobi5_f32 8192^2 block{blk[0]}x{blk[1]} c{cells} (per sweep, 100 sweeps)"] = {
+        res[jacobi_key(blk, cells)] = {
             "us": round(ms * 1e3, 2), "GB/s": round(byt / ms / 1e6, 1),
             "frac_hbm": round(byt / ms / 1e6 / HBM_PEAK_GBS, 4)}
     # JACOBI5T_F32: the same 100 sweeps, S fused per launch (temporal
@@ -452,13 +474,22 @@ def jacobi_workloads(spmd, synth):
             "us": round(ms * 1e3, 2), "GB/s_algorithmic": round(byt / ms / 1e6, 1),
             "hbm_bytes_per_sweep": int(moved), "GB/s_hbm_moved": round(moved / ms / 1e6, 1),
             "speedup_vs_one_sweep_per_launch": None}
-    base = res["jacobi5_f32 8192^2 block16x16 c1 (per sweep, 100 sweeps)"]["us"]
+    base = res[jacobi_key((16, 16), 1)]["us"]
     for k, v in res.items():
         if k.startswith("jacobi5t"):
             v["speedup_vs_one_sweep_per_launch"] = round(base / v["us"], 2)
     del u, a, bb
     torch.cuda.empty_cache()
     return res
+
+
+def jacobi_key(blk, cells):
+    """Record name of a one-sweep Jacobi launch: the launched block shape and
+    cells per thread, and the physical tile it runs as (the blocks of one
+    block row are fetched 256 columns at a time as a 64 x 4 workgroup)."""
+    rows = blk[1] * cells
+    phys = f", runs as 256-column tiles of {rows} rows on 64x4 workgroups" if 4 <= rows <= 64 else ""
+    return f"jacobi5_f32 8192^2 block{blk[0]}x{blk[1]} c{cells}{phys} (per sweep, 100 sweeps)"
 
 
 def chain_workloads(spmd, synth):
@@ -787,6 +818,80 @@ def cpu_baseline(xs_h, ks_h, step_bytes):
     return {"value": round(step_bytes / t / 1e9, 3), "unit": "GB/s", "cores": pool, "kind": "oracle",
             "sample": "the full step (scan 2^26 + hist 2^27) on the oracle's thread-pool executor, "
                       f"median of 3 runs, {t:.2f} s each"}
+
+
+def _median_seconds(fn, runs=3):
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_executor_baselines(mixed_count):
+    """The oracle's thread-pool executor (the paper's runtime: a pool of
+    workers fetching ceil(grid / pool) blocks at a time) on the other
+    workloads, with the GPU figures' algorithmic denominators:
+      * reduce 2^20 int32, grid 4096, block 256 (median of 3 runs);
+      * one Jacobi sweep of the 8192^2 grid in 16 x 16 blocks (one run);
+      * GEMM at 1024^3 instead of 4096^3 (one run; the executor needs
+        minutes at the full size);
+      * a seeded sample of 200 instances of the mixed workload, each as
+        launched (its blockDim, 4 items per thread; stencils in 16 x 16
+        blocks), one after the other.
+    Each row is a baseline, not the target."""
+    import oracle
+    import synth
+
+    from paper_2206_07896_amd import workload as W
+
+    pool = min(16, os.cpu_count() or 1)
+    res = {}
+    x = synth.uniform_int32(synth.SEED_REDUCE, 1 << 20, -1000, 1000)
+    oracle.reduce_i32(x[:4096], 16, 256, pool=pool)  # start the pool
+    t = _median_seconds(lambda: oracle.reduce_i32(x, 4096, 256, pool=pool))
+    nbytes = 4 * (1 << 20) + 4 * 4096 * 2 + 4
+    res["reduce_i32 2^20 g4096 b256"] = {"us": round(t * 1e6, 1), "GB/s": round(nbytes / t / 1e9, 3),
+                                         "cores": pool, "runs": 3}
+    u = synth.uniform_f32(synth.SEED_JACOBI, 8192 * 8192).reshape(8192, 8192)
+    t = _median_seconds(lambda: oracle.jacobi5_f32(u, 16, 16, pool=pool), runs=1)
+    res[jacobi_key((16, 16), 1)] = {
+        "us": round(t * 1e6, 1), "GB/s": round(8 * 8192 * 8192 / t / 1e9, 3), "cores": pool,
+        "sample": "one sweep"}
+    del u
+    m = 1024
+    A = synth.normal_f32(synth.SEED_GEMM, m * m).reshape(m, m)
+    B = synth.normal_f32(synth.SEED_GEMM + 1, m * m).reshape(m, m)
+    t = _median_seconds(lambda: oracle.gemm_f32(A, B, pool=pool), runs=1)
+    res["gemm_f32 4096^3 tile64"] = {"us": round(t * 1e6, 1), "TFLOP/s": round(2 * m ** 3 / t / 1e12, 6),
+                                     "cores": pool, "sample": "1024^3 instead of 4096^3"}
+    specs = W.mixed_specs(mixed_count)
+    rng = np.random.default_rng(0xC4)
+    sample = [specs[i] for i in sorted(rng.choice(len(specs), min(200, len(specs)), replace=False).tolist())]
+    inputs = [W.host_input(s) for s in sample]
+
+    def run_sample():
+        for s, xi in zip(sample, inputs):
+            k, bd, n = s["kid"], s["block_dim"], s["n"]
+            grid = max(1, -(-n // (bd * 4)))
+            if k == W.REDUCE_I32:
+                oracle.reduce_i32(xi, grid, bd, pool=pool)
+            elif k == W.SCAN_I32:
+                oracle.scan_i32(xi, bd, 4, pool=pool)
+            elif k == W.HIST256_U32:
+                oracle.hist256_u32(xi, grid, bd, pool=pool)
+            else:
+                oracle.jacobi5_f32(xi, 16, 16, pool=pool)
+
+    t = _median_seconds(run_sample, runs=1)
+    nbytes = sum(W.algorithmic_bytes(s) for s in sample)
+    res["mixed_queue"] = {"instances": len(sample), "seconds": round(t, 3),
+                          "launches_per_s": round(len(sample) / t, 1), "GB/s": round(nbytes / t / 1e9, 3),
+                          "cores": pool,
+                          "sample": f"200 instances drawn (seed 0xC4) from the {mixed_count}-instance workload"}
+    log(f"cpu oracle executor: {json.dumps(res)}")
+    return res
 
 
 if __name__ == "__main__":

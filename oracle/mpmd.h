@@ -65,7 +65,8 @@ enum {
     OX_W_SHFL,     /* v[seg + (p mod w)]                                   */
     OX_W_UP,       /* i < p ? own : v[lane - p]                             */
     OX_W_DOWN,     /* i + p >= w ? own : v[lane + p]                        */
-    OX_W_XOR,      /* (i ^ p) < w ? v[seg + (i ^ p)] : own                  */
+    OX_W_XOR,      /* j = lane ^ p; j <= seg + w - 1 ? v[j] : own (j may be  */
+                   /* in an earlier segment, as CUDA documents)              */
     OX_W_BALLOT,   /* sum over lanes of (pred != 0) << lane                 */
     OX_W_ANY,      /* ballot != 0                                           */
     OX_W_ALL,      /* ballot == 0xFFFFFFFF                                  */

@@ -37,7 +37,7 @@ from . import batch as B
 
 NFEAT, NSCHED, DIN, NPARAM = 9, 3, 12, 12 * 64 + 64 + 64 * 64 + 64 + 64 + 1
 KIND_IDS = (REDUCE_I32, SCAN_I32, HIST256_U32, JACOBI5_F32)
-# the library's candidate table: block 64..512, items 1..16, bpf 1..32
+# the library's candidate table: block 64..512, items 1..32 (32: scan tiles only), bpf 1..32
 CANDIDATES = B.sched_candidates()
 BLOCKS = tuple(sorted({b for b, _, _ in CANDIDATES}))
 
@@ -443,6 +443,52 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
         f"{ms_learned:.2f} batch-aware {ms_learned_ba:.2f} heuristic {ms_heur:.2f} exhaustive {ms_exh:.2f}")
     model.tau = tau
     return res, model
+
+
+def heldout_regret(model, count=200, seed=None, reps=2, log2_hi=22.0, log=None):
+    """Schedule regret of `model` on `count` launches drawn like the mixed
+    workload from `seed` (default: the held-out seed, never trained on),
+    each timed in this run under every valid candidate (the exhaustive
+    ground truth).  The model picks the least predicted time per launch;
+    with the fallback, launches whose ensemble spread exceeds the model's
+    threshold take the exhaustive choice instead.  The paper's heuristic
+    (blockDim as launched, 4 items per thread, average coarse-grained
+    fetching) is timed on the same launches for comparison."""
+    import time
+
+    import synth
+
+    from . import workload as W
+
+    seed = synth.SEED_HELDOUT if seed is None else seed
+    specs = W.mixed_specs(count, seed=seed, log2_hi=log2_hi)
+    data = W.MixedData(specs)
+    tuner = Autotuner(reps=reps)
+    t0 = time.perf_counter()
+    T = tuner.sweep(specs, data, progress=log)
+    items = data.items()
+    pools = pools_for()
+    heur = [heuristic_schedule(s, pools) for s in specs]
+    t_heur = np.array([tuner.time(items[i], [heur[i]])[0] for i in range(count)])
+    t_tune = time.perf_counter() - t0
+    choice, _, sd = model.choose(specs)
+    exhaustive = np.nanargmin(T, axis=1)
+    fb = sd > model.tau
+    best = np.nanmin(T, axis=1)
+    r = regret(T, choice)
+    r_fb = regret(T, np.where(fb, exhaustive, choice))
+    r_heur = (t_heur - best) / best
+    del data
+    return {
+        "heldout_launches": count, "seed": seed, "candidates": len(CANDIDATES),
+        "regret_mean": round(float(r.mean()), 4), "regret_median": round(float(np.median(r)), 4),
+        "regret_p90": round(float(np.quantile(r, 0.9)), 4),
+        "regret_mean_with_fallback": round(float(r_fb.mean()), 4),
+        "fallback_rate": round(float(fb.mean()), 4), "fallback_sd_threshold": round(float(model.tau), 4),
+        "regret_mean_heuristic": round(float(r_heur.mean()), 4),
+        "seconds_exhaustive_timing": round(t_tune, 1),
+        "timing": f"fastest of {reps} runs after a warm-up per (launch, schedule), each launch alone in a batch",
+    }
 
 
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_model.json")

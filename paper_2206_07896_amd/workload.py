@@ -110,15 +110,20 @@ class MixedData:
 
     def host_input(self, i):
         """The same input regenerated on the host (for checks)."""
-        s = self.specs[i]
-        k = s["kid"]
-        if k == REDUCE_I32:
-            return synth.uniform_int32(s["seed"], s["n"], -1000, 1000)
-        if k == SCAN_I32:
-            return synth.uniform_int32(s["seed"], s["n"], 0, 100)
-        if k == HIST256_U32:
-            return synth.zipf_u32(s["seed"], s["n"])
-        return synth.uniform_f32(s["seed"], s["n"]).reshape(s["ny"], s["nx"])
+        return host_input(self.specs[i])
+
+
+def host_input(s):
+    """Input of spec `s` generated on the host (the values MixedData fills on
+    the device)."""
+    k = s["kid"]
+    if k == REDUCE_I32:
+        return synth.uniform_int32(s["seed"], s["n"], -1000, 1000)
+    if k == SCAN_I32:
+        return synth.uniform_int32(s["seed"], s["n"], 0, 100)
+    if k == HIST256_U32:
+        return synth.zipf_u32(s["seed"], s["n"])
+    return synth.uniform_f32(s["seed"], s["n"]).reshape(s["ny"], s["nx"])
 
 
 def as_launched_schedules(specs, items: int = 4, workers_per_cu: int = 0):

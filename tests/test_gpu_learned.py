@@ -28,3 +28,21 @@ def test_learned_schedule_beats_heuristic_small():
     # the learned choice costs less in total than the paper's heuristic
     assert res["time_sum_ratio_heuristic_over_learned"] > 1.0
     assert res["regret_mean_with_fallback"] < res["regret_mean_heuristic"]
+
+
+def test_shipped_model_regret_within_bound():
+    """The shipped cost model on 150 held-out launches drawn like the mixed
+    workload (sizes up to 2^22), each timed here under every candidate
+    schedule: the mean regret of its choice, with the exhaustive fallback
+    for low-confidence launches, is at most 10%."""
+    import paper_2206_07896_amd  # noqa: F401
+    from paper_2206_07896_amd import learned as L
+
+    model = L.load_default()
+    assert model is not None, "the package ships a cost model"
+    print("case: shipped model, 150 held-out launches x every schedule", flush=True)
+    res = L.heldout_regret(model, 150)
+    print(res, flush=True)
+    assert 0.0 <= res["regret_mean_with_fallback"] <= res["regret_mean"] + 1e-12
+    assert res["regret_mean_with_fallback"] <= 0.10
+    assert res["regret_mean_with_fallback"] < res["regret_mean_heuristic"]
