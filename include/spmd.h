@@ -195,6 +195,32 @@ enum {
  * Returns SPMD_OK once the work is enqueued. */
 int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args, void* stream);
 
+/* spmd_launch for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same classes, shapes, semantics and errors as spmd_launch, except that
+ * the classes with a workspace (SPMD_REDUCE_I32, SPMD_SCAN_I32,
+ * SPMD_COMPACT_I32) take args WITHOUT their last parameter, the workspace:
+ * the launch uses instead a region of a static device array that the
+ * library holds on every device it runs on (SPMD_NOALLOC_REGION_BYTES per
+ * class, about 3 MiB per device in all, held until the process ends).
+ * Other classes are launched exactly as by spmd_launch.
+ *  - Limit: a grid whose workspace (spmd_workspace_size) exceeds
+ *    SPMD_NOALLOC_REGION_BYTES -- more than 2^17 blocks -- returns
+ *    SPMD_ERR_WORKSPACE before anything is enqueued.
+ *  - Allocation: none.  The call makes no hipMalloc/hipFree and calls no
+ *    allocating routine.  The library's per-device set-up (the first call
+ *    of any entry point on a device) looks the array up and clears it,
+ *    synchronously; make one call on a device before capturing a graph.
+ *  - Sharing: every launch of one class on one device uses the same region,
+ *    which keeps what the last launch left (the state its class's next
+ *    launch expects, so nothing needs clearing between calls).  Two such
+ *    launches of one class in flight at the same time on one device (two
+ *    streams, or a graph replay concurrent with a stream launch) race on
+ *    the region: the caller orders them. */
+#define SPMD_NOALLOC_REGION_BYTES ((1u << 20) + 16384u)
+int spmd_launch_noalloc(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args,
+                        void* stream);
+
 /* Bytes of workspace a launch of `kernel_id` with this grid and block needs
  * for n elements (0 when the class needs none). */
 size_t spmd_workspace_size(int kernel_id, spmd_dim3 grid, spmd_dim3 block, uint64_t n);

@@ -74,6 +74,8 @@ class SpmdError(RuntimeError):
 _P = ctypes.c_void_p
 _lib.spmd_launch.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P]
 _lib.spmd_launch.restype = ctypes.c_int
+_lib.spmd_launch_noalloc.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P]
+_lib.spmd_launch_noalloc.restype = ctypes.c_int
 _lib.spmd_workspace_size.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_uint64]
 _lib.spmd_workspace_size.restype = ctypes.c_size_t
 _lib.spmd_sync.argtypes = [_P]
@@ -137,10 +139,15 @@ def signature(kernel: int) -> str:
     return s.decode()
 
 
-def pack_args(kernel: int, args):
+# classes whose last parameter is a workspace (spmd_launch_noalloc leaves it out)
+WORKSPACE_CLASSES = (REDUCE_I32, SCAN_I32, COMPACT_I32)
+NOALLOC_REGION_BYTES = (1 << 20) + 16384  # SPMD_NOALLOC_REGION_BYTES
+
+
+def pack_args(kernel: int, args, sig=None):
     """The host prologue of the paper's parameter packing: one heap object
     per parameter, args[i] pointing at it.  Returns (void** array, keepalive)."""
-    sig = signature(kernel)
+    sig = signature(kernel) if sig is None else sig
     if len(args) != len(sig):
         raise SpmdError(-4, f"kernel {kernel} takes {len(sig)} arguments, got {len(args)}")
     objs = []
@@ -161,6 +168,19 @@ def launch(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None) -> Non
                           ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), _stream_handle(stream))
     del keep
     _check(rc, f"spmd_launch({_lib.spmd_kernel_name(kid).decode() if 1 <= kid <= NUM_KERNELS else kid})")
+
+
+def launch_noalloc(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None) -> None:
+    """spmd_launch_noalloc: as :func:`launch`, with the workspace argument of
+    REDUCE_I32, SCAN_I32 and COMPACT_I32 left out (the library's static
+    per-device scratch is used instead; nothing is allocated)."""
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    sig = signature(kid)
+    arr, keep = pack_args(kid, list(args), sig[:-1] if kid in WORKSPACE_CLASSES else sig)
+    rc = _lib.spmd_launch_noalloc(kid, _dim3(grid), _dim3(block), dyn_shmem,
+                                  ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), _stream_handle(stream))
+    del keep
+    _check(rc, f"spmd_launch_noalloc({_lib.spmd_kernel_name(kid).decode() if 1 <= kid <= NUM_KERNELS else kid})")
 
 
 def workspace_size(kernel, grid, block, n: int) -> int:

@@ -37,6 +37,7 @@ struct DevInfo {
     int num_cus;
     size_t max_shmem_per_block;
     uint32_t* err_word;  // device address of this device's error state (two words)
+    uint8_t* scratch;    // device address of this device's static scratch (noalloc.hip)
 };
 
 struct LaunchCtx {
@@ -84,6 +85,9 @@ inline void clear_stale_error() { (void)hipGetLastError(); }
 
 // State of the current device (created on first use with the device current).
 int runtime_dev(const DevInfo** out);
+// Device set-up of spmd_launch_noalloc's static scratch (noalloc.hip): its
+// device address on the current device, cleared.
+int noalloc_setup(uint8_t** out);
 
 // Class launchers (one translation unit each).  They validate the
 // class-specific rules and enqueue the work.

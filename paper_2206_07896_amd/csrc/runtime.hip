@@ -84,6 +84,8 @@ int runtime_dev(const DevInfo** out) {
         if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_error_word))) != hipSuccess) return hip_fail(e);
         di.err_word = static_cast<uint32_t*>(p);
         if ((e = hipMemset(di.err_word, 0, 2 * sizeof(uint32_t))) != hipSuccess) return hip_fail(e);
+        int rc = noalloc_setup(&di.scratch);
+        if (rc) return rc;
         g_dev_ready[d] = true;
     }
     *out = &g_dev[d];

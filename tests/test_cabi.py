@@ -95,6 +95,35 @@ def test_null_args(spmd):
     assert rc == -4
 
 
+def _raw_noalloc(spmd, kid, grid, block, args):
+    argp = None
+    if args is not None:
+        sig = spmd.signature(kid)
+        arr, keep = spmd.pack_args(kid, args, sig[:-1] if kid in spmd.WORKSPACE_CLASSES else sig)
+        argp = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    return spmd.lib().spmd_launch_noalloc(kid, spmd._dim3(grid), spmd._dim3(block), 0, argp, None)
+
+
+def test_noalloc_validation(spmd):
+    """spmd_launch_noalloc refuses, before touching a device: an unknown
+    class, missing arguments, a zero dimension, and a grid whose workspace
+    does not fit the static region (any grid of up to 2^17 blocks fits)."""
+    lib = spmd.lib()
+    assert lib.spmd_launch_noalloc(99, spmd._dim3(1), spmd._dim3(64), 0, None, None) == -1
+    for kid in spmd.WORKSPACE_CLASSES:
+        assert lib.spmd_launch_noalloc(kid, spmd._dim3(1), spmd._dim3(64), 0, None, None) == -4
+        args = [16] * (len(spmd.signature(kid)) - 1)  # never dereferenced: every case is refused
+        assert _raw_noalloc(spmd, kid, (0, 1, 1), 64, args) == -2
+        fits = 1 << 17
+        assert spmd.workspace_size(kid, fits, 64, 0) <= spmd.NOALLOC_REGION_BYTES
+        over = fits
+        while spmd.workspace_size(kid, over, 64, 0) <= spmd.NOALLOC_REGION_BYTES:
+            over += 1
+        assert _raw_noalloc(spmd, kid, over, 64, args) == -8
+    # a class without a workspace is validated as by spmd_launch
+    assert _raw_noalloc(spmd, spmd.HIST256_U32, 1, 2048, [16, 16, 16]) == -2
+
+
 def test_binding_arity_check(spmd):
     with pytest.raises(spmd.SpmdError) as e:
         spmd.pack_args(spmd.SCAN_I32, [0, 0])
