@@ -150,6 +150,103 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
+// Rows form of a full, 16-byte aligned tile with I >= 4: wave w owns
+// elements [w*64*I, (w+1)*64*I) of the tile as I/4 rows of 64 lanes x 4
+// consecutive elements.  `wx` / `wy` point at the wave's first element.
+template <int I>
+__device__ __forceinline__ void scan_rows_load(const int32_t* __restrict__ wx, uint32_t lane, u32x4 (&r)[I / 4]) {
+    const u32x4* xv = reinterpret_cast<const u32x4*>(wx);
+#pragma unroll
+    for (int q = 0; q < I / 4; ++q) r[q] = __builtin_nontemporal_load(xv + q * 64 + lane);
+}
+
+// In-wave inclusive scan of the rows in place (each row where it lies: the
+// lane's four values, then the 32-lane scan of the lane totals on each
+// half-wavefront, the halves joined by lane 31's total, rows chained by
+// their totals).  Returns the wave's total (wave-uniform).
+template <int I>
+__device__ __forceinline__ uint32_t scan_rows_local(uint32_t lane, u32x4 (&r)[I / 4]) {
+    uint32_t carry = 0;  // total of the rows before row q
+#pragma unroll
+    for (int q = 0; q < I / 4; ++q) {
+        r[q].y += r[q].x;
+        r[q].z += r[q].y;
+        r[q].w += r[q].z;
+        uint32_t incl = w32_inclusive_add(r[q].w);
+        incl += lane >= 32u ? (uint32_t)__builtin_amdgcn_readlane((int)incl, 31) : 0u;
+        const uint32_t before = incl - r[q].w + carry;
+        r[q].x += before;
+        r[q].y += before;
+        r[q].z += before;
+        r[q].w += before;
+        carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    }
+    return carry;
+}
+
+template <int I>
+__device__ __forceinline__ void scan_rows_store(int32_t* __restrict__ wy, uint32_t lane, const u32x4 (&r)[I / 4],
+                                                uint32_t pre) {
+    u32x4* yv = reinterpret_cast<u32x4*>(wy);
+#pragma unroll
+    for (int q = 0; q < I / 4; ++q) {
+        u32x4 a = r[q];
+        a.x += pre;
+        a.y += pre;
+        a.z += pre;
+        a.w += pre;
+        __builtin_nontemporal_store(a, yv + q * 64 + lane);
+    }
+}
+
+// Block totals of the per-wave (or per-warp) sums in LDS: the tile's
+// aggregate and the sum of the slots before `mine`.
+template <int NSLOT>
+__device__ __forceinline__ void scan_slot_sums(const uint32_t* slot, uint32_t mine, uint32_t& agg, uint32_t& before) {
+    agg = 0;
+    before = 0;
+#pragma unroll
+    for (int w = 0; w < NSLOT; ++w) {
+        const uint32_t s = slot[w];
+        agg += s;
+        before += ((uint32_t)w < mine) ? s : 0u;
+    }
+}
+
+// Items form (partial or unaligned tiles, and I < 4): each thread scans I
+// consecutive items, then the 32-lane scan of the thread totals.
+template <int B, int I, typename Hook = NoHook>
+__device__ __forceinline__ void scan_tile_items(const int32_t* __restrict__ x, int32_t* __restrict__ y, uint32_t n,
+                                                uint32_t tile, uint64_t* status, uint32_t tag, uint32_t* err,
+                                                ScanLds<B, I>& L, Hook after_lookback = Hook()) {
+    constexpr int NW = B / 32;
+    const uint32_t t = threadIdx.x;
+    const uint64_t base = (uint64_t)tile * ((uint64_t)B * I) + (uint64_t)t * I;
+    uint32_t v[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
+#pragma unroll
+    for (int k = 1; k < I; ++k) v[k] += v[k - 1];
+    const uint32_t tot = v[I - 1];
+    const uint32_t wincl = w32_inclusive_add(tot);
+    if ((t & 31u) == 31u) L.warp[t >> 5] = wincl;
+    __syncthreads();
+    uint32_t agg, wpre;
+    scan_slot_sums<NW>(L.warp, t >> 5, agg, wpre);
+    if (t < 64) {
+        const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
+        if (t == 0) {
+            L.excl = excl;
+            after_lookback();
+        }
+    }
+    __syncthreads();
+    const uint32_t pre = L.excl + wpre + (wincl - tot);
+#pragma unroll
+    for (int k = 0; k < I; ++k)
+        if (base + k < n) y[base + k] = (int32_t)(pre + v[k]);
+}
+
 // Scan tile `tile` of x into y.  The caller places a barrier before the LDS
 // area is reused.  Thread 0 calls `after_lookback` once the tile's
 // inclusive prefix is published, i.e. once no other tile can wait on this
@@ -163,38 +260,15 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
     const uint64_t tbase = (uint64_t)tile * T;
     if constexpr (I >= 4) {
         if (vec && tbase + T <= (uint64_t)n) {
-            constexpr int S = I / 4;  // rows per wave
-            constexpr int NWAVE = B / 64;
             const uint32_t lane = lane64(), wave = t >> 6;
             const uint64_t wbase = tbase + (uint64_t)wave * 64u * I;
-            const u32x4* xv = reinterpret_cast<const u32x4*>(x + wbase);
-            u32x4 r[S];
-#pragma unroll
-            for (int q = 0; q < S; ++q) r[q] = __builtin_nontemporal_load(xv + q * 64 + lane);
-            uint32_t carry = 0;  // wave-uniform: total of the rows before row q
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                r[q].y += r[q].x;
-                r[q].z += r[q].y;
-                r[q].w += r[q].z;
-                uint32_t incl = w32_inclusive_add(r[q].w);
-                incl += lane >= 32u ? (uint32_t)__builtin_amdgcn_readlane((int)incl, 31) : 0u;
-                const uint32_t before = incl - r[q].w + carry;
-                r[q].x += before;
-                r[q].y += before;
-                r[q].z += before;
-                r[q].w += before;
-                carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            }
+            u32x4 r[I / 4];
+            scan_rows_load<I>(x + wbase, lane, r);
+            const uint32_t carry = scan_rows_local<I>(lane, r);
             if (lane == 0) L.warp[wave] = carry;
             __syncthreads();
-            uint32_t wpre = 0, agg = 0;
-#pragma unroll
-            for (int w = 0; w < NWAVE; ++w) {
-                const uint32_t s = L.warp[w];
-                agg += s;
-                wpre += ((uint32_t)w < wave) ? s : 0u;
-            }
+            uint32_t agg, wpre;
+            scan_slot_sums<B / 64>(L.warp, wave, agg, wpre);
             if (t < 64) {
                 const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
                 if (t == 0) {
@@ -203,52 +277,11 @@ __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t
                 }
             }
             __syncthreads();
-            const uint32_t pre = L.excl + wpre;
-            u32x4* yv = reinterpret_cast<u32x4*>(y + wbase);
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                u32x4 a = r[q];
-                a.x += pre;
-                a.y += pre;
-                a.z += pre;
-                a.w += pre;
-                __builtin_nontemporal_store(a, yv + q * 64 + lane);
-            }
+            scan_rows_store<I>(y + wbase, lane, r, L.excl + wpre);
             return;
         }
     }
-    // items path: partial or unaligned tiles, and I < 4
-    constexpr int NW = B / 32;
-    const uint64_t base = tbase + (uint64_t)t * I;
-    uint32_t v[I];
-#pragma unroll
-    for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;
-#pragma unroll
-    for (int k = 1; k < I; ++k) v[k] += v[k - 1];
-    const uint32_t tot = v[I - 1];
-    const uint32_t wincl = w32_inclusive_add(tot);
-    if ((t & 31u) == 31u) L.warp[t >> 5] = wincl;
-    __syncthreads();
-    uint32_t wpre = 0, agg = 0;
-    const uint32_t mywarp = t >> 5;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const uint32_t s = L.warp[w];
-        agg += s;
-        wpre += ((uint32_t)w < mywarp) ? s : 0u;
-    }
-    if (t < 64) {
-        const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
-        if (t == 0) {
-            L.excl = excl;
-            after_lookback();
-        }
-    }
-    __syncthreads();
-    const uint32_t pre = L.excl + wpre + (wincl - tot);
-#pragma unroll
-    for (int k = 0; k < I; ++k)
-        if (base + k < n) y[base + k] = (int32_t)(pre + v[k]);
+    scan_tile_items<B, I>(x, y, n, tile, status, tag, err, L, after_lookback);
 }
 
 }  // namespace spmd
