@@ -833,11 +833,11 @@ def cpu_executor_baselines(mixed_count):
     """The oracle's thread-pool executor (the paper's runtime: a pool of
     workers fetching ceil(grid / pool) blocks at a time) on the other
     workloads, with the GPU figures' algorithmic denominators:
-      * reduce 2^20 int32, grid 4096, block 256 (median of 3 runs);
-      * one Jacobi sweep of the 8192^2 grid in 16 x 16 blocks (one run);
-      * GEMM at 1024^3 instead of 4096^3 (one run; the executor needs
-        minutes at the full size);
-      * a seeded sample of 200 instances of the mixed workload, each as
+      * reduce 2^20 int32, grid 4096, block 256 (median of 5 runs);
+      * one Jacobi sweep of the 8192^2 grid in 16 x 16 blocks (median of 3);
+      * GEMM at 2048^3 instead of 4096^3 (one run; the executor needs
+        about a minute at the full size);
+      * a seeded sample of 1000 instances of the mixed workload, each as
         launched (its blockDim, 4 items per thread; stencils in 16 x 16
         blocks), one after the other.
     Each row is a baseline, not the target."""
@@ -850,25 +850,25 @@ def cpu_executor_baselines(mixed_count):
     res = {}
     x = synth.uniform_int32(synth.SEED_REDUCE, 1 << 20, -1000, 1000)
     oracle.reduce_i32(x[:4096], 16, 256, pool=pool)  # start the pool
-    t = _median_seconds(lambda: oracle.reduce_i32(x, 4096, 256, pool=pool))
+    t = _median_seconds(lambda: oracle.reduce_i32(x, 4096, 256, pool=pool), runs=5)
     nbytes = 4 * (1 << 20) + 4 * 4096 * 2 + 4
     res["reduce_i32 2^20 g4096 b256"] = {"us": round(t * 1e6, 1), "GB/s": round(nbytes / t / 1e9, 3),
-                                         "cores": pool, "runs": 3}
+                                         "cores": pool, "runs": 5}
     u = synth.uniform_f32(synth.SEED_JACOBI, 8192 * 8192).reshape(8192, 8192)
-    t = _median_seconds(lambda: oracle.jacobi5_f32(u, 16, 16, pool=pool), runs=1)
+    t = _median_seconds(lambda: oracle.jacobi5_f32(u, 16, 16, pool=pool), runs=3)
     res[jacobi_key((16, 16), 1)] = {
         "us": round(t * 1e6, 1), "GB/s": round(8 * 8192 * 8192 / t / 1e9, 3), "cores": pool,
-        "sample": "one sweep"}
+        "sample": "one sweep, median of 3"}
     del u
-    m = 1024
+    m = 2048
     A = synth.normal_f32(synth.SEED_GEMM, m * m).reshape(m, m)
     B = synth.normal_f32(synth.SEED_GEMM + 1, m * m).reshape(m, m)
     t = _median_seconds(lambda: oracle.gemm_f32(A, B, pool=pool), runs=1)
     res["gemm_f32 4096^3 tile64"] = {"us": round(t * 1e6, 1), "TFLOP/s": round(2 * m ** 3 / t / 1e12, 6),
-                                     "cores": pool, "sample": "1024^3 instead of 4096^3"}
+                                     "cores": pool, "sample": "2048^3 instead of 4096^3"}
     specs = W.mixed_specs(mixed_count)
     rng = np.random.default_rng(0xC4)
-    sample = [specs[i] for i in sorted(rng.choice(len(specs), min(200, len(specs)), replace=False).tolist())]
+    sample = [specs[i] for i in sorted(rng.choice(len(specs), min(1000, len(specs)), replace=False).tolist())]
     inputs = [W.host_input(s) for s in sample]
 
     def run_sample():
@@ -889,7 +889,7 @@ def cpu_executor_baselines(mixed_count):
     res["mixed_queue"] = {"instances": len(sample), "seconds": round(t, 3),
                           "launches_per_s": round(len(sample) / t, 1), "GB/s": round(nbytes / t / 1e9, 3),
                           "cores": pool,
-                          "sample": f"200 instances drawn (seed 0xC4) from the {mixed_count}-instance workload"}
+                          "sample": f"{len(sample)} instances drawn (seed 0xC4) from the {mixed_count}-instance workload"}
     log(f"cpu oracle executor: {json.dumps(res)}")
     return res
 
