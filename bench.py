@@ -733,9 +733,9 @@ def mixed_queue(spmd, count, reps=10):
         # aware: the fewest chunks within SPMD_BATCH_SLACK of it (the choice
         # spmd_launch_batch makes in SPMD_SCHED_LEARNED mode)
         for key, slack, what in (("learned", None, "cost model, least predicted time per launch, no fallback"),
-                                 ("learned_batch", L.BATCH_SLACK,
-                                  f"cost model, batch-aware: fewest chunks within {L.BATCH_SLACK:.0%} of the least "
-                                  "predicted time, no fallback")):
+                                 ("learned_batch", model.slack,
+                                  f"cost model, batch-aware: fewest chunks within {model.slack:.0%} of the least "
+                                  "predicted time (the model's slack, chosen on held-out launches), no fallback")):
             choice, _, sd = model.choose(specs, slack=slack)
             sched = [L.CANDIDATES[j] for j in choice]
             bl = spmd.batch.Batch(data.items(), sched)

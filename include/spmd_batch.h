@@ -166,7 +166,8 @@ enum {
      * coarse-grained fetching, ceil(blocks / pool) per fetch (Section IV-A) */
     SPMD_SCHED_AS_LAUNCHED = 0,
     /* under the loaded cost model (spmd_model_load), batch-aware: among
-     * the schedules predicted within SPMD_BATCH_SLACK of the least, the one
+     * the schedules predicted within the model's slack (SPMD_BATCH_SLACK
+     * unless spmd_model_batch_slack set another) of the least, the one
      * with the fewest chunks (spmd_mlp_choose_batch); launches whose
      * ensemble spread exceeds the model's threshold are tuned exhaustively
      * instead (spmd_tune_time over every candidate, fastest alone), and
@@ -174,9 +175,12 @@ enum {
     SPMD_SCHED_LEARNED = 1
 };
 
-/* Slack of the batch-aware learned choice: 20% over the least predicted
- * time buys fewer chunks to fetch (measured on the 10 000-launch mixed
- * queue: 6.3 ms against 8.8 ms for the least predicted time per launch). */
+/* Default slack of the batch-aware learned choice: 20% over the least
+ * predicted time buys fewer chunks to fetch (measured on the 10 000-launch
+ * mixed queue: 6.3 ms against 8.8 ms for the least predicted time per
+ * launch).  The best slack depends on the model; a trained model carries
+ * its own, chosen on held-out launches, and sets it with
+ * spmd_model_batch_slack. */
 #define SPMD_BATCH_SLACK 0.2f
 
 /* Chunk counts of n launches under every candidate schedule (the order of
@@ -216,6 +220,14 @@ int spmd_launch_batch_report(spmd_batch_report* out);
  * the model (params and norm may then be NULL).  The device copies are the
  * library's own until the next load or unload. */
 int spmd_model_load(const float* params, uint32_t k_models, const float* norm, float sd_threshold);
+
+/* Slack of SPMD_SCHED_LEARNED's batch-aware choice for the model loaded on
+ * the current device: the fewest chunks among the schedules predicted
+ * within ln(1 + slack) of the least (the grain-size trade-off of the
+ * paper's coarse-grained fetching, Section IV-A, made per launch).
+ * spmd_model_load resets it to SPMD_BATCH_SLACK.  SPMD_ERR_ARGS without a
+ * loaded model, or for a negative or non-finite slack. */
+int spmd_model_batch_slack(float slack);
 
 /* The candidate schedules the tuner and the cost model range over, in
  * their fixed order (block 64..512, then items 1..32, then bpf 1..32; 144

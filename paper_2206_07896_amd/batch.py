@@ -204,6 +204,8 @@ _lib.spmd_launch_batch_report.argtypes = [ctypes.POINTER(BatchReport)]
 _lib.spmd_launch_batch_report.restype = ctypes.c_int
 _lib.spmd_model_load.argtypes = [_P, _U32, _P, ctypes.c_float]
 _lib.spmd_model_load.restype = ctypes.c_int
+_lib.spmd_model_batch_slack.argtypes = [ctypes.c_float]
+_lib.spmd_model_batch_slack.restype = ctypes.c_int
 _lib.spmd_sched_candidates.argtypes = [ctypes.POINTER(Schedule), _U32]
 _lib.spmd_sched_candidates.restype = _U32
 _lib.spmd_sched_features.argtypes = [ctypes.POINTER(BatchItem), ctypes.POINTER(ctypes.c_float)]
@@ -261,15 +263,18 @@ def launch_batch_report() -> dict:
     return {"launches": r.launches, "by_model": r.by_model, "tuned": r.tuned, "cached": r.cached}
 
 
-def model_load(params, norm, sd_threshold: float = float("inf")) -> None:
+def model_load(params, norm, sd_threshold: float = float("inf"), slack: float | None = None) -> None:
     """Load a cost model (host arrays: [k, NPARAM] parameters, 24 norm
-    values) for SCHED_LEARNED on the current device."""
+    values) for SCHED_LEARNED on the current device, with its batch-aware
+    slack (None: the library's default)."""
     import numpy as np
 
     p = np.ascontiguousarray(params, dtype=np.float32)
     k = p.shape[0] if p.ndim == 2 else 1
     nm = np.ascontiguousarray(norm, dtype=np.float32)
     _check(_lib.spmd_model_load(p.ctypes.data, k, nm.ctypes.data, float(sd_threshold)), "spmd_model_load")
+    if slack is not None and k:
+        _check(_lib.spmd_model_batch_slack(float(slack)), "spmd_model_batch_slack")
 
 
 def sched_candidates():

@@ -54,6 +54,7 @@ struct Model {
     float* norm = nullptr;    // device, 2 * DIN
     uint32_t k = 0;
     float tau = INFINITY;
+    float slack = SPMD_BATCH_SLACK;  // of the batch-aware choice
     std::map<CacheKey, spmd_schedule> tuned;
 };
 
@@ -228,6 +229,7 @@ int spmd_model_load(const float* params, uint32_t k_models, const float* norm, f
     m.params = nullptr;
     m.norm = nullptr;
     m.k = 0;
+    m.slack = SPMD_BATCH_SLACK;
     m.tuned.clear();
     if (e != hipSuccess) return hip_fail(e);
     if (!k_models) return SPMD_OK;  // unloaded
@@ -238,6 +240,18 @@ int spmd_model_load(const float* params, uint32_t k_models, const float* norm, f
     if ((e = hipMemcpy(m.norm, norm, nb, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e);
     m.k = k_models;
     m.tau = sd_threshold;
+    return SPMD_OK;
+}
+
+int spmd_model_batch_slack(float slack) {
+    if (!(slack >= 0.0f) || !(slack < 1e30f)) return SPMD_ERR_ARGS;
+    int d = 0;
+    int rc = current_device(&d);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Model& m = g_model[d];
+    if (!m.k) return SPMD_ERR_ARGS;
+    m.slack = slack;
     return SPMD_OK;
 }
 
@@ -313,7 +327,7 @@ int spmd_launch_batch(const spmd_launch_desc* descs, int n, int mode, void* work
         if (e != hipSuccess) return hip_fail(e);
         rc = spmd_mlp_choose_batch(m.params, m.k, m.norm, reinterpret_cast<const float*>(ws + IL.feats), (uint32_t)n,
                                    reinterpret_cast<const float*>(ws + IL.cands), NCANDS, ws + IL.valid,
-                                   reinterpret_cast<const uint32_t*>(ws + IL.chunks), SPMD_BATCH_SLACK,
+                                   reinterpret_cast<const uint32_t*>(ws + IL.chunks), m.slack,
                                    reinterpret_cast<uint32_t*>(ws + IL.best), reinterpret_cast<float*>(ws + IL.pred),
                                    reinterpret_cast<float*>(ws + IL.sd), stream);
         if (rc) return rc;

@@ -54,7 +54,8 @@ _lib.spmd_mlp_choose_batch.argtypes = [_P, ctypes.c_uint32, _P, _P, ctypes.c_uin
 _lib.spmd_mlp_choose_batch.restype = ctypes.c_int
 _lib.spmd_sched_chunks.argtypes = [ctypes.POINTER(B.BatchItem), ctypes.c_int, _P]
 _lib.spmd_sched_chunks.restype = ctypes.c_int
-BATCH_SLACK = 0.2  # SPMD_BATCH_SLACK
+BATCH_SLACK = 0.2  # SPMD_BATCH_SLACK, the library's default
+SLACK_CHOICES = (0.1, 0.2, 0.3, 0.5, 1.0, 2.0)  # tried on held-out launches for each trained model
 for _f in ("spmd_mlp_forward", "spmd_mlp_backward", "spmd_mlp_adam", "spmd_mlp_choose"):
     getattr(_lib, _f).restype = ctypes.c_int
 _lib.spmd_tune_workspace_size.argtypes = [ctypes.POINTER(B.BatchItem), ctypes.POINTER(B.Schedule), ctypes.c_int]
@@ -171,6 +172,7 @@ class CostModel:
         self.norm = np.asarray(norm, np.float32).reshape(2 * DIN)
         self.k = self.params.shape[0]
         self.tau = float("inf")  # ensemble spread above which the exhaustive fallback runs
+        self.slack = BATCH_SLACK  # of the batch-aware choice (SPMD_SCHED_LEARNED)
         self._dev = None
 
     def device_tensors(self):
@@ -180,7 +182,7 @@ class CostModel:
         return self._dev
 
     def to_json(self) -> str:
-        return json.dumps({"k": self.k, "tau": self.tau, "norm": self.norm.tolist(),
+        return json.dumps({"k": self.k, "tau": self.tau, "slack": self.slack, "norm": self.norm.tolist(),
                            "params": self.params.tolist()})
 
     @staticmethod
@@ -188,7 +190,13 @@ class CostModel:
         d = json.loads(text)
         m = CostModel(np.array(d["params"], np.float32), np.array(d["norm"], np.float32))
         m.tau = float(d.get("tau", float("inf")))
+        m.slack = float(d.get("slack", BATCH_SLACK))
         return m
+
+    def load(self) -> None:
+        """Load this model into the library for SPMD_SCHED_LEARNED on the
+        current device (its fallback threshold and batch slack with it)."""
+        B.model_load(self.params, self.norm, self.tau, self.slack)
 
     def predict(self, X: np.ndarray, model: int = 0) -> np.ndarray:
         """Predicted log-microseconds of rows X[n x 12] under one model."""
@@ -308,6 +316,25 @@ def train(X: np.ndarray, t: np.ndarray, k_models: int = 3, steps: int = 3000, lr
     return model, losses
 
 
+def select_batch_slack(model, specs, items, slacks=SLACK_CHOICES, reps=10, log=None):
+    """The batch-aware slack for `model`: each slack's choice for the
+    launches `specs` (with their device items) is run as one batch replayed
+    from a hipGraph (median of `reps` replays); the fastest slack wins.
+    Returns (slack, {slack: ms})."""
+    table = {}
+    for slack in slacks:
+        choice = model.choose(specs, slack=slack)[0]
+        b = B.Batch(items, [CANDIDATES[j] for j in choice])
+        try:
+            table[slack] = round(_median_graph_ms(b, reps), 4)
+        finally:
+            b.close()
+        if log is not None:
+            log(f"  slack {slack}: {table[slack]:.3f} ms")
+    best = min(table, key=lambda k: (table[k], k))
+    return best, table
+
+
 def regret(T, choice):
     """Per-launch (t_chosen - t_best) / t_best from exhaustive timings."""
     best = np.nanmin(T, axis=1)
@@ -404,6 +431,7 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
     chunks_ho = sched_chunks(specs_ho).astype(np.int64)
     ms_learned = batch_ms(sched_learned)
     ms_learned_ba = batch_ms([CANDIDATES[j] for j in choice_ba])
+    model.slack, slack_ms = select_batch_slack(model, specs_ho, items, reps=batch_reps, log=log)
     ms_heur = batch_ms(heur)
     ms_exh = batch_ms(sched_exh)
     del data_ho
@@ -429,6 +457,7 @@ def evaluate(train_count=500, heldout_count=2000, k_models=3, steps=2000, lr=3e-
         "per_class": per_class,
         "batch_ms_learned": round(ms_learned, 3), "batch_ms_heuristic": round(ms_heur, 3),
         "batch_ms_exhaustive": round(ms_exh, 3), "batch_ms_learned_batch_aware": round(ms_learned_ba, 3),
+        "batch_slack": model.slack, "batch_ms_by_slack": {str(k): v for k, v in slack_ms.items()},
         "chunks_learned": int(chunks_ho[np.arange(heldout_count), choice_fb].sum()),
         "chunks_learned_batch_aware": int(chunks_ho[np.arange(heldout_count), choice_ba].sum()),
         "launches_per_s_learned": round(heldout_count / (ms_learned * 1e-3), 1),
@@ -562,12 +591,33 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--out", default=MODEL_PATH)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--select-slack", action="store_true",
+                    help="only choose the shipped model's batch-aware slack on the held-out launches and write it back")
     ap.add_argument("--contention", action="store_true",
                     help="only time histograms of skewed keys under every schedule (no training)")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if a.select_slack:
+        import synth
+
+        from . import workload as W
+
+        model = load_default()
+        specs = W.mixed_specs(a.heldout, seed=synth.SEED_HELDOUT)
+        data = W.MixedData(specs)
+        model.slack, table = select_batch_slack(model, specs, data.items(), log=log)
+        with open(a.out, "w") as f:
+            f.write(model.to_json())
+        text = json.dumps({"heldout_launches": a.heldout, "batch_slack": model.slack,
+                           "batch_ms_by_slack": {str(k): v for k, v in table.items()}})
+        print(text, flush=True)
+        if a.report:
+            with open(a.report, "w") as f:
+                f.write(text + "\n")
+        return
 
     if a.contention:
         rows = contention_study(load_default(), log=log)

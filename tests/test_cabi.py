@@ -124,6 +124,13 @@ def test_noalloc_validation(spmd):
     assert _raw_noalloc(spmd, spmd.HIST256_U32, 1, 2048, [16, 16, 16]) == -2
 
 
+def test_model_batch_slack_validation(spmd):
+    """A negative or non-finite slack is refused before any device call."""
+    lib = spmd.batch._lib
+    for bad in (-1.0, float("nan"), float("inf")):
+        assert lib.spmd_model_batch_slack(bad) == -4
+
+
 def test_binding_arity_check(spmd):
     with pytest.raises(spmd.SpmdError) as e:
         spmd.pack_args(spmd.SCAN_I32, [0, 0])

@@ -485,8 +485,8 @@ def test_mixed_workload_configured_size(spmd):
     class uniform over the four batchable classes, n = round(2^U) with
     U ~ U[10, 22] (about 5e9 elements), blockDim uniform over 64..512, run
     by spmd_launch_batch under SPMD_SCHED_LEARNED with the shipped cost
-    model and its fallback threshold (low-confidence launches are tuned
-    exhaustively first).  Every instance with n <= 2^14 and a seeded sample
+    model, its fallback threshold (low-confidence launches are tuned
+    exhaustively first) and its batch slack.  Every instance with n <= 2^14 and a seeded sample
     of 200 larger ones are compared with the oracle; the whole output arena
     must then equal, byte for byte, the batch-aware learned plan that the
     measurement replays from a graph (model choice without fallback) and
@@ -502,7 +502,7 @@ def test_mixed_workload_configured_size(spmd):
     data = W.MixedData(specs)
     launches = [_launch_desc(spmd, W, data, i) for i in range(len(specs))]
     say("mixed workload 10000 launches, SCHED_LEARNED, tau", model.tau)
-    spmd.batch.model_load(model.params, model.norm, model.tau)
+    model.load()
     try:
         data.outputs.fill_(-1)
         ws = spmd.batch.launch_batch(launches, spmd.batch.SCHED_LEARNED)
@@ -526,7 +526,7 @@ def test_mixed_workload_configured_size(spmd):
         g = data.output_of(i).cpu().numpy()
         assert np.array_equal(g, want.reshape(g.shape)), (i, specs[i]["kid"], specs[i]["n"])
     # the measured plan (batch-aware learned choice, graph replay) and the baseline
-    choice, _, _ = model.choose(specs, slack=L.BATCH_SLACK)
+    choice, _, _ = model.choose(specs, slack=model.slack)
     b = spmd.batch.Batch(data.items(), [L.CANDIDATES[j] for j in choice])
     for mode in ("graph", "graph", "each"):
         say("mixed workload 10000", mode)

@@ -102,3 +102,30 @@ def test_learned_and_fallback_match_oracle(spmd):
     rep = spmd.batch.launch_batch_report()
     assert rep["cached"] == 24 and rep["tuned"] == 0
     spmd.batch._lib.spmd_model_load(None, 0, None, 0.0)
+
+
+def test_model_batch_slack(spmd):
+    """spmd_model_batch_slack sets the loaded model's batch-aware slack:
+    refused without a model or for a negative or non-finite slack; with a
+    model, learned batches at slacks from 0 (least predicted time only) to
+    2 (up to 3x the least) all match the oracle."""
+    from oracle import mlp as omlp
+
+    lib = spmd.batch._lib
+    lib.spmd_model_load(None, 0, None, 0.0)
+    assert lib.spmd_model_batch_slack(0.5) == -4  # no model loaded
+    params = np.stack([omlp.init_params(s) for s in (4, 5)]).astype(np.float32)
+    norm = np.concatenate([np.zeros(12), np.ones(12)]).astype(np.float32)
+    spmd.batch.model_load(params, norm, float("inf"))
+    for bad in (-0.1, float("nan"), float("inf")):
+        assert lib.spmd_model_batch_slack(bad) == -4
+    insts = make_instances(spmd, 16, 14, nmax_log2=12)
+    descs = descs_of(spmd, insts)
+    for slack in (0.0, 0.2, 2.0):
+        say("launch_batch learned, slack", slack)
+        spmd.batch.model_load(params, norm, float("inf"), slack)
+        scribble(insts)
+        spmd.batch.launch_batch(descs, spmd.batch.SCHED_LEARNED)
+        spmd.sync()
+        check_all(insts, f"slack {slack}")
+    lib.spmd_model_load(None, 0, None, 0.0)
