@@ -58,14 +58,20 @@ struct ScanLds {
 constexpr int LOOKBACK_PER_LANE = 2;
 constexpr int LOOKBACK_WINDOW = 64 * LOOKBACK_PER_LANE;
 
+__device__ __forceinline__ void scan_publish_agg(uint64_t* status, uint32_t tile, uint32_t agg, uint32_t tag) {
+    status_put(status + tile, status_pack(agg, tile == 0 ? SCAN_INCL : SCAN_AGG, tag));
+}
+
+// `published`: the caller has already published the tile's aggregate
+// (scan_publish_agg), so only the wait and the inclusive prefix remain.
 __device__ __forceinline__ uint32_t scan_lookback(uint64_t* status, uint32_t tile, uint32_t agg, uint32_t tag,
-                                                  uint32_t* err) {
+                                                  uint32_t* err, bool published = false) {
     const uint32_t lane = lane64();
     if (tile == 0) {
-        if (lane == 0) status_put(status, status_pack(agg, SCAN_INCL, tag));
+        if (lane == 0 && !published) status_put(status, status_pack(agg, SCAN_INCL, tag));
         return 0;
     }
-    if (lane == 0) status_put(status + tile, status_pack(agg, SCAN_AGG, tag));
+    if (lane == 0 && !published) status_put(status + tile, status_pack(agg, SCAN_AGG, tag));
     const uint32_t limit = spin_limit(err);
     uint32_t spins = 0, nap = 1;
     while (status_flag(status_get(status + tile - 1), tag) == 0u) {

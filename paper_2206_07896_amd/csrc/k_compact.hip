@@ -5,9 +5,12 @@
 // status word per tile.  As for the scan, the kernel is persistent:
 // min(G, resident) blocks take tiles from the ticket in order, so every
 // look-back wait is for a tile a running block holds; a block draws its
-// next tile once its current tile is stored (no workgroup launch between
+// next tile once its current tile is staged (no workgroup launch between
 // tiles), and the launch's last draw (G + blocks - 1) re-arms the ticket
-// and advances the epoch.
+// and advances the epoch.  A tile's count is published before the block
+// waits for anything (its first tile) or once the previous tile's
+// look-back has ended (every later tile); that look-back waits only for
+// smaller tiles, so by induction over the tile index every wait ends.
 #include <algorithm>
 
 #include "cls_compact.hpp"
@@ -30,25 +33,62 @@ __global__ __launch_bounds__(B) void compact_i32_kernel(const int32_t* __restric
                                                          uint32_t* count, uint32_t n, int32_t t, uint32_t ntiles,
                                                          uint32_t* ws, uint32_t* err, bool vec) {
     __shared__ CompactLds<B, I> L;
-    __shared__ uint32_t s_tile, s_next, s_tag;
+    __shared__ uint32_t s_next, s_tag;
     uint64_t* ticket = reinterpret_cast<uint64_t*>(ws);
     uint64_t* status = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(ws) + COMPACT_WS_HEADER);
-    if (threadIdx.x == 0) s_tile = compact_draw(ticket, ntiles, &s_tag);
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_next = compact_draw(ticket, ntiles, &s_tag);
     __syncthreads();
-    uint32_t tile = s_tile;
     const uint32_t tag = s_tag;
-    while (tile < ntiles) {
-        compact_tile<B, I>(x, y, count, n, t, tile, ntiles, status, tag, err, vec, L, NoHook());
-        // The next tile is drawn only once this one is stored.  Drawn
-        // earlier (after the look-back, with or without its loads issued
-        // during this tile's copy-out) it starts its own stage late and
-        // holds up its successors' look-back: measured slower.
-        if (threadIdx.x == 0) {
+    uint32_t t0 = s_next;  // block-uniform
+    if (t0 >= ntiles) return;
+    CompactFront<B, I> F;
+    uint32_t agg0, wpre;
+    compact_issue<B, I>(x, n, t0, vec, F);
+    compact_count<B, I>(x, n, t, t0, F, L);
+    __syncthreads();
+    compact_sums<B, I>(L, agg0, wpre);
+    if (tid == 0) scan_publish_agg(status, t0, agg0, tag);
+    compact_stage<B, I>(x, n, t, t0, wpre, F, L);
+    if (tid == 0) {
+        uint32_t unused;
+        s_next = compact_draw(ticket, ntiles, &unused);
+    }
+    __syncthreads();  // t0 staged, s_next visible
+    // Tile t0 is staged and its count published.  The next tile t1 is drawn
+    // already: its loads are issued before t0's look-back, and its count is
+    // published before t0's copy-out, so no successor waits on t1 for the
+    // length of t0's copy-out.
+    for (;;) {
+        const uint32_t t1 = s_next;
+        const bool has1 = t1 < ntiles;
+        if (has1) compact_issue<B, I>(x, n, t1, vec, F);
+        if (tid < 64) {
+            const uint32_t excl = scan_lookback(status, t0, agg0, tag, err, true);
+            if (tid == 0) {
+                L.excl = excl;
+                if (t0 == ntiles - 1) *count = excl + agg0;
+            }
+        }
+        if (has1) compact_count<B, I>(x, n, t, t1, F, L);
+        __syncthreads();  // L.excl, and t1's warp counts
+        uint32_t agg1 = 0;
+        if (has1) {
+            compact_sums<B, I>(L, agg1, wpre);
+            if (tid == 0) scan_publish_agg(status, t1, agg1, tag);
+        }
+        int32_t* yo = y + L.excl;
+        for (uint32_t i = tid; i < agg0; i += B) yo[i] = (int32_t)L.stage[i];
+        __syncthreads();  // the stage, L.excl and L.warp are free again
+        if (!has1) break;
+        compact_stage<B, I>(x, n, t, t1, wpre, F, L);
+        if (tid == 0) {
             uint32_t unused;
             s_next = compact_draw(ticket, ntiles, &unused);
         }
-        __syncthreads();  // s_next is written; the LDS stage is free again
-        tile = s_next;
+        __syncthreads();
+        t0 = t1;
+        agg0 = agg1;
     }
 }
 
