@@ -58,6 +58,7 @@ struct ScanLds {
 constexpr int LOOKBACK_PER_LANE = 2;
 constexpr int LOOKBACK_WINDOW = 64 * LOOKBACK_PER_LANE;
 
+// A tile's aggregate as its status word; tile 0's is its inclusive prefix.
 __device__ __forceinline__ void scan_publish_agg(uint64_t* status, uint32_t tile, uint32_t agg, uint32_t tag) {
     status_put(status + tile, status_pack(agg, tile == 0 ? SCAN_INCL : SCAN_AGG, tag));
 }
