@@ -345,7 +345,13 @@ def _gemm_gate(C, c64, K):
 
 @pytest.mark.parametrize("tile", [64, 128, 256])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 64, 16), (65, 63, 17), (128, 96, 130), (3, 200, 5), (257, 130, 64),
-                                   (512, 512, 512)])
+                                   (512, 512, 512),
+                                   # 16-byte rows (N, K multiples of 4): the direct-to-LDS form, with
+                                   # K below one slice, K tails of 4 / 8 / 12, slice counts on both
+                                   # sides of its pipeline's main loop, and rows / columns past C
+                                   (1, 4, 4), (33, 68, 8), (100, 124, 12), (64, 64, 32), (70, 260, 48),
+                                   (130, 132, 96), (129, 256, 112), (200, 196, 116), (256, 256, 200),
+                                   (300, 300, 1028)])
 def test_gemm_shapes(spmd, tile, M, N, K):
     say("gemm", M, N, K, tile)
     A = synth.normal_f32(M * 7 + K, M * K).reshape(M, K)
@@ -372,6 +378,27 @@ def test_gemm_exact_cases(spmd, tile):
     C2 = host(spmd.ops.gemm_f32(dev(A2), dev(np.eye(77, dtype=np.float32)), tile=tile))
     spmd.sync()
     assert np.array_equal(C2, A2)
+
+
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_gemm_grid_larger_than_c(spmd, tile):
+    """A grid with more tiles than C needs: the extra blocks store nothing
+    (C sits between guard words that must stay as they were)."""
+    import torch
+
+    M, N, K = 150, 100, 68
+    say("gemm oversized grid", tile)
+    A = synth.normal_f32(5, M * K).reshape(M, K)
+    B = synth.normal_f32(6, K * N).reshape(K, N)
+    guard = 1 << 12
+    buf = torch.full((M * N + 2 * guard,), 7.0, dtype=torch.float32, device="cuda")
+    C = buf[guard:guard + M * N]
+    grid = (-(-N // tile) + 3, -(-M // tile) + 2)
+    spmd.launch(spmd.GEMM_F32, grid, 256, 0, [dev(A), dev(B), C, M, N, K])
+    spmd.sync()
+    got = host(buf)
+    assert np.all(got[:guard] == 7.0) and np.all(got[guard + M * N:] == 7.0)
+    assert _gemm_gate(got[guard:guard + M * N].reshape(M, N), oracle.gemm_f64(A, B), K)
 
 
 @pytest.mark.parametrize("tile", [64, 128, 256])
@@ -540,6 +567,29 @@ def test_compact_edges(spmd):
     y, count = spmd.ops.compact_i32(empty, 0)
     spmd.sync()
     assert int(count.item()) == 0
+
+
+@pytest.mark.parametrize("block,items", [(256, 16), (1024, 32)])
+def test_compact_many_tiles_per_block(spmd, block, items):
+    """Thousands of tiles, so each persistent block runs its two-tile
+    pipeline many times: an unaligned input (every tile takes the
+    element-wise passes) and an aligned one with a ragged tail (row tiles,
+    then a partial last tile in the same pipeline), against the oracle."""
+    import torch
+
+    n = (1 << 22) + 777
+    x = synth.uniform_int32(0xC1E, n + 1, -1000, 1000)
+    base = dev(x)
+    for off in (1, 0):
+        say("compact many tiles", block, items, "offset", off)
+        xt = base[off:off + n]
+        want = oracle.compact_i32(x[off:off + n], 0)
+        y, count = spmd.ops.compact_i32(xt, 0, block, items)
+        spmd.sync()
+        m = int(count.item())
+        assert m == want.size, (off, m, want.size)
+        bad = np.flatnonzero(host(y)[:m] != want)
+        assert bad.size == 0, (off, bad[:5])
 
 
 @pytest.mark.parametrize("block,items", [(256, 16), (1024, 32), (512, 32)])
