@@ -109,6 +109,44 @@ __device__ __forceinline__ bool reduce_ticket_last(uint32_t* ctl, uint32_t G, ui
     return true;
 }
 
+// The finishing block: sum the `count` status words (eight independent
+// loads in flight per thread; only words not yet visible are polled
+// again), write *out and advance the epoch, so words of this launch -- even
+// one stored late, after a wait gave up -- read as unwritten in the next.
+template <int B>
+__device__ __forceinline__ void reduce_final(uint64_t* status, uint32_t count, uint32_t tag, uint32_t* ctl,
+                                             int32_t* out, uint32_t* err, ReduceLds<B>& L) {
+    const uint32_t limit = spin_limit(err);
+    uint32_t acc = 0;
+    for (uint32_t j0 = threadIdx.x; j0 < count; j0 += 8u * B) {
+        uint64_t w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t j = j0 + (uint32_t)q * B;
+            w[q] = j < count ? status_get(status + j) : status_pack(0u, 1u, tag);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint32_t j = j0 + (uint32_t)q * B;
+            for (uint32_t spins = 0; status_flag(w[q], tag) == 0u; ++spins) {
+                if (spins >= limit) {
+                    atomicOr(err, ERRBIT_SPIN_LIMIT);
+                    w[q] = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                w[q] = status_get(status + j);
+            }
+            acc += (uint32_t)(w[q] >> 32);
+        }
+    }
+    const uint32_t total = block_sum_t0<B>(acc, L);
+    if (threadIdx.x == 0) {
+        *out = (int32_t)total;
+        put_dev(ctl + REDUCE_EPOCH_WORD, tag + 1u);  // every block of this launch has read the epoch
+    }
+}
+
 // One logical block `bid` of a G-block reduction.  Cross-block state
 // (`ctl`, `status`): `ctl` holds the two-level completion ticket and the
 // launch epoch (REDUCE_CTL_BYTES), status[b] the partial of block b as a
@@ -138,38 +176,85 @@ __device__ __forceinline__ bool reduce_block(const int32_t* __restrict__ x, int3
     const uint32_t tag = L.epoch;
     __syncthreads();
     if (!last) return false;
-    // The G status words, eight independent loads in flight per thread;
-    // only words not yet visible are polled again.
-    const uint32_t limit = spin_limit(err);
-    uint32_t acc = 0;
-    for (uint32_t j0 = threadIdx.x; j0 < G; j0 += 8u * B) {
-        uint64_t w[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t j = j0 + (uint32_t)q * B;
-            w[q] = j < G ? status_get(status + j) : status_pack(0u, 1u, tag);
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t j = j0 + (uint32_t)q * B;
-            for (uint32_t spins = 0; status_flag(w[q], tag) == 0u; ++spins) {
-                if (spins >= limit) {
-                    atomicOr(err, ERRBIT_SPIN_LIMIT);
-                    w[q] = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                w[q] = status_get(status + j);
-            }
-            acc += (uint32_t)(w[q] >> 32);
-        }
-    }
-    const uint32_t total = block_sum_t0<B>(acc, L);
-    if (threadIdx.x == 0) {
-        *out = (int32_t)total;
-        put_dev(ctl + REDUCE_EPOCH_WORD, tag + 1u);  // every block of this launch has read the epoch
-    }
+    reduce_final<B>(status, G, tag, ctl, out, err, L);
     return true;
+}
+
+
+// K consecutive logical blocks [K w, K w + K) of a G-block reduction run by
+// workgroup w of P (the launcher's persistent form: P covers the device's
+// resident workgroups, so fewer workgroups than logical blocks each keep
+// more loads in flight).  Each logical block's sum is computed and written
+// to `partials` exactly as a block of its own would; one status word and
+// one completion ticket per workgroup carry the workgroup's total, and the
+// finishing workgroup sums the P totals.
+template <int B, int K>
+__device__ __forceinline__ void reduce_blocks(const int32_t* __restrict__ x, int32_t* partials, int32_t* out,
+                                              uint32_t n, uint32_t seg, uint32_t G, uint32_t P, uint32_t w,
+                                              uint32_t* ctl, uint64_t* status, uint32_t* err, bool vec,
+                                              ReduceLds<B>& L, uint32_t (&wsum)[K][B / 64]) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t b0 = w * K;
+    const uint32_t epoch = t == 0 ? load_dev(ctl + REDUCE_EPOCH_WORD) : 0u;
+    uint32_t acc[K];
+    uint64_t lo[K], hi[K], nv[K];
+    uint64_t nvmax = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        acc[j] = 0;
+        lo[j] = (uint64_t)(b0 + j) * seg;
+        hi[j] = b0 + j < G ? (lo[j] + seg < (uint64_t)n ? lo[j] + seg : (uint64_t)n) : lo[j];
+        if (hi[j] < lo[j]) hi[j] = lo[j];
+        nv[j] = vec ? (hi[j] - lo[j]) >> 2 : 0;  // whole 16-byte groups (seg is a multiple of 4)
+        nvmax = nv[j] > nvmax ? nv[j] : nvmax;
+    }
+    // the K segments' 16-byte groups, four rows of B per segment in flight
+    const u32x4* xv = reinterpret_cast<const u32x4*>(x);
+    for (uint64_t v0 = t; v0 < nvmax; v0 += 4u * B) {
+        u32x4 a[K][4];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t v = v0 + (uint64_t)q * B;
+                a[j][q] = v < nv[j] ? __builtin_nontemporal_load(xv + (lo[j] >> 2) + v) : u32x4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[j] += (a[j][q].x + a[j][q].y) + (a[j][q].z + a[j][q].w);
+    }
+    // what is left: the last segment's tail, or everything when unaligned
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        for (uint64_t e = lo[j] + (nv[j] << 2) + t; e < hi[j]; e += B) acc[j] += (uint32_t)x[e];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const uint32_t s = wave_sum(acc[j]);
+        if (lane64() == 0) wsum[j][t / 64] = s;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t total = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            uint32_t s = 0;
+#pragma unroll
+            for (int i = 0; i < B / 64; ++i) s += wsum[j][i];
+            if (b0 + j < G) {
+                if (partials) partials[b0 + j] = (int32_t)s;
+                total += s;
+            }
+        }
+        status_put(status + w, status_pack(total, 1u, epoch));
+        L.last = reduce_ticket_last(ctl, P, w) ? 1u : 0u;
+        L.epoch = epoch;
+    }
+    __syncthreads();
+    const bool last = L.last != 0u;
+    const uint32_t tag = L.epoch;
+    __syncthreads();
+    if (last) reduce_final<B>(status, P, tag, ctl, out, err, L);
 }
 
 }  // namespace spmd

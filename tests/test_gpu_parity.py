@@ -81,7 +81,11 @@ def test_warp_conformance(spmd, grid, block):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,grid,block", [(1, 1, 64), (1000, 3, 64), (12345, 37, 256), (1 << 16, 64, 1024),
-                                          (100003, 4096, 128), (1 << 20, 4096, 256)])
+                                          (100003, 4096, 128), (1 << 20, 4096, 256),
+                                          # grids past the resident workgroups: 2, 4 and 8 logical blocks per
+                                          # workgroup, with ragged and empty trailing segments
+                                          (3 * (1 << 20) + 1, 8192, 256), ((1 << 20) + 3, 16384, 256),
+                                          (500001, 8192, 64), (1 << 22, 65536, 512)])
 def test_reduce(spmd, n, grid, block):
     say("reduce", n, grid, block)
     x = synth.uniform_int32(synth.SEED_REDUCE + n, n, -1000, 1000)
@@ -100,11 +104,12 @@ def test_reduce_wrapping_and_unaligned(spmd):
     n = 50001
     x = synth.uniform_int32(99, n, -(2**31), 2**31 - 1)
     xt = dev(x)
-    want_p, want_t = oracle.reduce_i32(x[1:], 13, 256)
-    p, out = spmd.ops.reduce_i32(xt[1:], 13, 256)  # 4-byte offset: scalar load path
-    spmd.sync()
-    assert int(host(out)[0]) == want_t
-    assert np.array_equal(host(p), want_p)
+    for grid in (13, 4096):  # one logical block per workgroup, then two
+        want_p, want_t = oracle.reduce_i32(x[1:], grid, 256)
+        p, out = spmd.ops.reduce_i32(xt[1:], grid, 256)  # 4-byte offset: scalar load path
+        spmd.sync()
+        assert int(host(out)[0]) == want_t, grid
+        assert np.array_equal(host(p), want_p), grid
 
 
 # --------------------------------------------------------------------------
