@@ -90,7 +90,7 @@ enum {
      * args: const int32_t* x, int32_t* y, uint32_t n, void* workspace
      * grid (G,1,1), block (B,1,1), B in {64,128,256,512,1024}.  Block g
      * (in the order blocks start) scans a tile of B*I consecutive elements,
-     * I = the smallest power of two >= ceil(n / (G*B)); I <= 32 (I <= 64 for B <= 512).
+     * I = the smallest power of two >= ceil(n / (G*B)); I <= 32 (I <= 128 for B <= 512).
      * x and y may not overlap (SPMD_ERR_ARGS). */
     SPMD_SCAN_I32 = 2,
 

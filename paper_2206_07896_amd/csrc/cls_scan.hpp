@@ -229,6 +229,37 @@ __device__ __forceinline__ void scan_tile_items(const int32_t* __restrict__ x, i
     constexpr int NW = B / 32;
     const uint32_t t = threadIdx.x;
     const uint64_t base = (uint64_t)tile * ((uint64_t)B * I) + (uint64_t)t * I;
+    if constexpr (I > 64) {
+        // Two rolled passes (the thread's total, then after the look-back
+        // the running prefix, re-reading x), so this path neither grows the
+        // registers nor unrolls into the code of the rows loop it shares a
+        // kernel with: fully unrolled at 128 items it made that kernel
+        // three times larger and its full tiles 3% slower.
+        uint32_t tot = 0;
+#pragma unroll 4
+        for (int k = 0; k < I; ++k) tot += (base + k < n) ? (uint32_t)x[base + k] : 0u;
+        const uint32_t wincl = w32_inclusive_add(tot);
+        if ((t & 31u) == 31u) L.warp[t >> 5] = wincl;
+        __syncthreads();
+        uint32_t agg, wpre;
+        scan_slot_sums<NW>(L.warp, t >> 5, agg, wpre);
+        if (t < 64) {
+            const uint32_t excl = scan_lookback(status, tile, agg, tag, err);
+            if (t == 0) {
+                L.excl = excl;
+                after_lookback();
+            }
+        }
+        __syncthreads();
+        uint32_t run = L.excl + wpre + (wincl - tot);
+#pragma unroll 4
+        for (int k = 0; k < I; ++k)
+            if (base + k < n) {
+                run += (uint32_t)x[base + k];
+                y[base + k] = (int32_t)run;
+            }
+        return;
+    }
     uint32_t v[I];
 #pragma unroll
     for (int k = 0; k < I; ++k) v[k] = (base + k < n) ? (uint32_t)x[base + k] : 0u;

@@ -84,6 +84,9 @@ static void launch_b(uint32_t I, uint32_t G, size_t dyn, hipStream_t s, const in
     case 64:
         if constexpr (B <= 512) launch_bi<B, 64>(G, dyn, s, x, y, n, ws, err, vec, num_cus);
         break;
+    case 128:
+        if constexpr (B <= 512) launch_bi<B, 128>(G, dyn, s, x, y, n, ws, err, vec, num_cus);
+        break;
     }
 }
 
@@ -100,7 +103,7 @@ int launch_scan_i32(const LaunchCtx& c) {
     if (!ws || !aligned(ws, 16)) return SPMD_ERR_WORKSPACE;
     const uint64_t per = ((uint64_t)n + (uint64_t)c.grid.x * B - 1) / ((uint64_t)c.grid.x * B);
     const uint32_t I = next_pow2(per ? (uint32_t)per : 1u);
-    if (I > 64 || (I == 64 && B > 512)) return SPMD_ERR_INVALID_DIM;
+    if (I > 128 || (I >= 64 && B > 512)) return SPMD_ERR_INVALID_DIM;  // 1024 x 64 would spill
     if (n == 0) return SPMD_OK;
     const bool vec = aligned(x, 16) && aligned(y, 16);
     const uint32_t G = c.grid.x;

@@ -118,7 +118,8 @@ def test_reduce_wrapping_and_unaligned(spmd):
 
 @pytest.mark.parametrize("n,block,items", [(1, 64, 1), (100, 64, 1), (5000, 64, 4), (8193, 128, 8), (70001, 512, 16),
                                            (200000, 1024, 32), (123457, 256, 2), (300001, 512, 64),
-                                           (65536 * 3 + 17, 256, 64), (40000, 512, 32)])
+                                           (65536 * 3 + 17, 256, 64), (40000, 512, 32),
+                                           (65536 * 5 + 3, 512, 128), (100001, 256, 128), (1000, 64, 128)])
 def test_scan(spmd, n, block, items):
     say("scan", n, block, items)
     x = synth.uniform_int32(synth.SEED_SCAN + n, n, -(2**31), 2**31 - 1)
@@ -133,11 +134,32 @@ def test_scan(spmd, n, block, items):
         assert np.array_equal(got, want), (rep, int(np.argmax(got != want)))
 
 
-@pytest.mark.parametrize("items", [16, 32, 64])
+@pytest.mark.parametrize("block,items", [(512, 128), (256, 128), (512, 32)])
+def test_scan_unaligned(spmd, block, items):
+    """A 4-byte offset input and output: every tile takes the element-wise
+    path (at 128 items its two passes, the second re-reading x), over many
+    tiles and a ragged end, against the oracle."""
+    import torch
+
+    n = 3 * block * items * 7 + 11
+    say("scan unaligned", n, block, items)
+    x = synth.uniform_int32(0x5CA, n, -(2**31), 2**31 - 1)
+    want = oracle.scan_i32(x, block=64, items=4)
+    base = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    base[1:] = dev(x)
+    out = torch.full((n + 1,), 7, dtype=torch.int32, device="cuda")
+    spmd.ops.scan_i32(base[1:], block, items, y=out[1:])
+    spmd.sync()
+    got = host(out)
+    assert got[0] == 7
+    assert np.array_equal(got[1:], want), int(np.argmax(got[1:] != want))
+
+
+@pytest.mark.parametrize("items", [16, 32, 64, 128])
 def test_scan_workload_size(spmd, items):
-    """2^26 int32 U[0, 100] at blockDim 512 -- at 64 items the measured
-    step's launch (2048 tiles over the resident blocks, so every block loops
-    over several tiles), launched as the step does: twice on one workspace,
+    """2^26 int32 U[0, 100] at blockDim 512 -- at 128 items the measured
+    step's launch (1024 tiles over the resident blocks, one per CU, so every
+    block loops over several tiles), launched as the step does: twice on one workspace,
     into two outputs.  Checked over all 2^26 elements by the complete
     invariant (y[0] = x[0], y[i] - y[i-1] = x[i] mod 2^32) and against the
     oracle on a 2^20 prefix."""
@@ -153,7 +175,9 @@ def test_scan_workload_size(spmd, items):
         spmd.ops.scan_i32(xt, 512, items, y=y, ws=ws)
     spmd.sync()
     xu = x.view(np.uint32)
-    want_prefix = oracle.scan_i32(x[:1 << 20], 512, items)  # a prefix of the scan is the scan of the prefix
+    # a prefix of the scan is the scan of the prefix, whatever the launch shape
+    # (the oracle's executor holds at most 64 items per thread)
+    want_prefix = oracle.scan_i32(x[:1 << 20], 512, min(items, 64))
     for rep, y in enumerate(ys):
         got = host(y).view(np.uint32)
         assert got[0] == xu[0], rep
