@@ -21,6 +21,7 @@ Progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -38,6 +39,7 @@ SCAN_N = 1 << 26
 HIST_N = 1 << 27
 SCAN_BLOCK, SCAN_ITEMS = 512, 128
 HIST_GRID, HIST_BLOCK = 256, 1024
+SETTLE_S = 0.5  # untimed repetitions of the step before the warm-up steps
 
 
 def log(*a):
@@ -99,7 +101,7 @@ def measure(fn, reps, warmup=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
@@ -154,28 +156,52 @@ def main():
     scan_grid = spmd.ops.scan_grid(SCAN_N, SCAN_BLOCK, SCAN_ITEMS)
     ws = spmd.ops.workspace(spmd.SCAN_I32, scan_grid, SCAN_BLOCK, SCAN_N)
 
-    t_scan, t_hist = Timer(), Timer()
+    # One event between consecutive launches (each kernel's duration is the
+    # span between the events on either side of it): a second marker per
+    # boundary would add its own processing to every gap of the step.
+    marks = []
+
+    def mark():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        marks.append(e)
 
     def step(i):
-        s = t_scan.start()
         spmd.ops.scan_i32(xs[i & 1], SCAN_BLOCK, SCAN_ITEMS, y=ys[i & 1], ws=ws)
-        t_scan.stop(s)
-        s = t_hist.start()
+        mark()
         spmd.ops.hist256_u32(ks[i & 1], HIST_GRID, HIST_BLOCK, hist=hist)
-        t_hist.stop(s)
+        mark()
 
+    # Settle: repeat the step untimed for half a second first, so the timed
+    # steps do not run while the GPU's clocks are still ramping up from idle
+    # (on a fresh box the first milliseconds of HBM-bound work run ~8% slow).
+    t_settle = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t_settle < SETTLE_S:
+        for _ in range(8):
+            step(i)
+            i += 1
+        torch.cuda.synchronize()
     for i in range(args.warmup):
         step(i)
     spmd.sync()
-    t_scan.pairs.clear()
-    t_hist.pairs.clear()
 
     torch.cuda.synchronize()
+    marks.clear()
+    # as timeit does: no cyclic-GC pass of the host harness inside the timed
+    # steps (one would leave the GPU idle for milliseconds)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
+    mark()
     for i in range(args.steps):
         step(args.warmup + i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
+    t_scan, t_hist = Timer(), Timer()
+    t_scan.pairs = [(marks[2 * i], marks[2 * i + 1]) for i in range(args.steps)]
+    t_hist.pairs = [(marks[2 * i + 1], marks[2 * i + 2]) for i in range(args.steps)]
     spmd.sync()  # raises if a kernel reported a device-side error
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
@@ -212,7 +238,7 @@ def main():
         "traffic": measured_traffic(dom[0]),
         "bytes_per_launch": dom[1],
         "avg_launch_us": round(dom[2] * 1e3, 2),
-        "timing": "HIP events on the launch stream around each launch over the timed steps",
+        "timing": "HIP events on the launch stream between consecutive launches over the timed steps",
     }
 
     kernels = {

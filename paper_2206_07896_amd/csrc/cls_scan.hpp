@@ -285,10 +285,13 @@ __device__ __forceinline__ void scan_tile_items(const int32_t* __restrict__ x, i
         if (base + k < n) y[base + k] = (int32_t)(pre + v[k]);
 }
 
-// Scan tile `tile` of x into y.  The caller places a barrier before the LDS
-// area is reused.  Thread 0 calls `after_lookback` once the tile's
-// inclusive prefix is published, i.e. once no other tile can wait on this
-// one any more.
+// Scan tile `tile` of x into y.  Thread 0 calls `after_lookback` once the
+// tile's inclusive prefix is published, i.e. once no other tile can wait on
+// this one any more.  Every thread's last access to L comes after the
+// tile's second (last) barrier and is a read of L.excl, and a tile writes L
+// only before its first barrier (L.warp) or by thread 0 between the two
+// (L.excl): back-to-back scan tiles need no barrier between them, a caller
+// that puts anything else in the area places one first.
 template <int B, int I, typename Hook = NoHook>
 __device__ __forceinline__ void scan_tile(const int32_t* __restrict__ x, int32_t* __restrict__ y, uint32_t n,
                                           uint32_t tile, uint64_t* status, uint32_t tag, uint32_t* err, bool vec,

@@ -52,7 +52,10 @@ __global__ __launch_bounds__(B) void scan_i32_kernel(const int32_t* __restrict__
             s_next = scan_draw(ticket, ntiles, &unused);
         };
         scan_tile<B, I>(x, y, n, tile, status, tag, err, vec, L, draw_next);
-        __syncthreads();  // s_next is written; the LDS area is free again
+        // No barrier here: s_next is written before the tile's second
+        // barrier, and thread 0 writes it, L.excl and L.warp again only after
+        // the next tile's first barrier, which every thread reaches after
+        // its last read of them.
         tile = s_next;
     }
 }
