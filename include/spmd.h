@@ -195,6 +195,24 @@ enum {
  * Returns SPMD_OK once the work is enqueued. */
 int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args, void* stream);
 
+/* spmd_launch with its kernels' device time: Section V's roofline places a
+ * kernel by its execution time alone, without the host or the stream
+ * around it.  `start_event` and `stop_event` are hipEvent_t handles created
+ * with timing enabled and owned by the caller; `stop_event` must not be
+ * null (SPMD_ERR_ARGS).  The start event is bound to the launch's first
+ * kernel dispatch and the stop event to its last, so
+ * hipEventElapsedTime(start, stop) is the time from the first kernel's start
+ * to the last kernel's end, with no marker packet of hipEventRecord's on
+ * the stream.  A null `start_event` binds the stop event alone, which costs
+ * the stream nothing (a bound start event costs about as much as a
+ * marker): the span is then taken from an earlier event, such as the stop
+ * event of the launch before, and also holds the gap between the two
+ * launches.  A launch that enqueues no kernel (n = 0) records its events on
+ * `stream` together.  Otherwise as spmd_launch, with the same errors; on an
+ * error no event is recorded. */
+int spmd_launch_timed(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args, void* stream,
+                      void* start_event, void* stop_event);
+
 /* spmd_launch for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same classes, shapes, semantics and errors as spmd_launch, except that

@@ -74,6 +74,8 @@ class SpmdError(RuntimeError):
 _P = ctypes.c_void_p
 _lib.spmd_launch.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P]
 _lib.spmd_launch.restype = ctypes.c_int
+_lib.spmd_launch_timed.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P, _P, _P]
+_lib.spmd_launch_timed.restype = ctypes.c_int
 _lib.spmd_launch_noalloc.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p), _P]
 _lib.spmd_launch_noalloc.restype = ctypes.c_int
 _lib.spmd_workspace_size.argtypes = [ctypes.c_int, Dim3, Dim3, ctypes.c_uint64]
@@ -160,14 +162,51 @@ def pack_args(kernel: int, args, sig=None):
     return arr, objs
 
 
-def launch(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None) -> None:
-    """spmd_launch: enqueue one grid of class ``kernel`` (id or name)."""
+def launch(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None, events=None) -> None:
+    """spmd_launch: enqueue one grid of class ``kernel`` (id or name).  With
+    ``events=(start, stop)`` (two :func:`timing_events`), spmd_launch_timed:
+    ``start.elapsed_time(stop)`` is then the device time of the launch's
+    kernels.  ``start`` may be None: only ``stop`` is bound (free on the
+    stream), to be measured from an earlier event."""
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     arr, keep = pack_args(kid, list(args))
-    rc = _lib.spmd_launch(kid, _dim3(grid), _dim3(block), dyn_shmem,
-                          ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), _stream_handle(stream))
+    argv = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    if events is None:
+        rc = _lib.spmd_launch(kid, _dim3(grid), _dim3(block), dyn_shmem, argv, _stream_handle(stream))
+        what = "spmd_launch"
+    else:
+        start, stop = (_event_handle(e) for e in events)
+        if stop is None:
+            raise ValueError("events=(start, stop): stop must be an event")
+        rc = _lib.spmd_launch_timed(kid, _dim3(grid), _dim3(block), dyn_shmem, argv, _stream_handle(stream),
+                                    start, stop)
+        what = "spmd_launch_timed"
     del keep
-    _check(rc, f"spmd_launch({_lib.spmd_kernel_name(kid).decode() if 1 <= kid <= NUM_KERNELS else kid})")
+    if rc:
+        _check(rc, f"{what}({_lib.spmd_kernel_name(kid).decode() if 1 <= kid <= NUM_KERNELS else kid})")
+
+
+def timing_events(count: int = 2):
+    """``count`` torch.cuda.Events with timing enabled whose HIP events
+    exist (each recorded once on the current stream), for ``events=`` of
+    :func:`launch` and the ops."""
+    import torch
+
+    out = []
+    for _ in range(count):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        out.append(e)
+    return out
+
+
+def _event_handle(e) -> int | None:
+    if e is None:
+        return None
+    h = e if isinstance(e, int) else int(e.cuda_event)
+    if not h:
+        raise ValueError("the event has no HIP event yet: take it from timing_events() or record it once")
+    return h
 
 
 def launch_noalloc(kernel, grid, block, dyn_shmem: int = 0, args=(), stream=None) -> None:

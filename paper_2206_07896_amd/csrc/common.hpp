@@ -4,6 +4,7 @@
 // III-C2: parameter i is read from the object args[i] points to), and the
 // device error bits.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -76,6 +77,31 @@ inline uint64_t segment_len(uint32_t n, uint32_t grid) {
 }
 
 int hip_fail(hipError_t e);  // records the HIP error text, returns SPMD_ERR_HIP
+
+// Events of a timed launch (spmd_launch_timed), null outside one.  The
+// start event (if any) is bound to the launch's first kernel dispatch and
+// the stop event to every dispatch, the last one standing, so the span
+// between them is the device time of the launch's kernels and no marker
+// packet sits between the launch and its neighbours on the stream.
+struct LaunchEvents {
+    hipEvent_t start, stop;
+    bool used;  // a dispatch has taken them
+};
+extern thread_local LaunchEvents g_launch_events;
+
+// Every kernel dispatch of spmd_launch's class launchers goes through here.
+template <typename F, typename... Args>
+inline void dispatch(F kernel, const dim3& grid, const dim3& block, uint32_t dyn_shmem, hipStream_t stream,
+                     Args... args) {
+    LaunchEvents& ev = g_launch_events;
+    if (ev.stop) {
+        hipExtLaunchKernelGGL(kernel, grid, block, dyn_shmem, stream, ev.used ? nullptr : ev.start, ev.stop, 0u,
+                              args...);
+        ev.used = true;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, dyn_shmem, stream, args...);
+    }
+}
 
 // The runtime keeps the error of the last failing call until it is read.
 // Entry points clear one that earlier, unrelated calls (another library's)

@@ -47,17 +47,17 @@ int launch_gemm_f32(const LaunchCtx& c) {
     const bool dma = vecA && vecB && (uint64_t)T * K < (1ull << 31) && (uint64_t)GEMM_DMA_KT * N < (1ull << 31);
     if (dma) {
         if (T == 64)
-            hipLaunchKernelGGL((gemm_f32_dma_kernel<64, 4>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
+            dispatch((gemm_f32_dma_kernel<64, 4>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
         else if (T == 128)
-            hipLaunchKernelGGL((gemm_f32_dma_kernel<128, 4>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
+            dispatch((gemm_f32_dma_kernel<128, 4>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
         else
-            hipLaunchKernelGGL((gemm_f32_dma_kernel<256, 3>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
+            dispatch((gemm_f32_dma_kernel<256, 3>), g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K);
     } else if (T == 64)
-        hipLaunchKernelGGL(gemm_f32_kernel<64>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+        dispatch(gemm_f32_kernel<64>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
     else if (T == 128)
-        hipLaunchKernelGGL(gemm_f32_kernel<128>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+        dispatch(gemm_f32_kernel<128>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
     else  // 128 x 128 per wave: 256 accumulators in AGPRs, one wave per SIMD
-        hipLaunchKernelGGL(gemm_f32_kernel<256>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
+        dispatch(gemm_f32_kernel<256>, g, b, c.dyn_shmem, c.stream, A, B, C, M, N, K, vecA, vecB);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }

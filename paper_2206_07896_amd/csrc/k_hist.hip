@@ -29,15 +29,15 @@ int launch_hist256_u32(const LaunchCtx& c) {
     if (seg64 > 0xFFFFFFFFull) return SPMD_ERR_INVALID_DIM;
     const uint32_t seg = (uint32_t)seg64;
     const bool vec = aligned(keys, 16);
-    hipLaunchKernelGGL(hist_clear_kernel, dim3(1), dim3(256), 0, c.stream, hist);
+    dispatch(hist_clear_kernel, dim3(1), dim3(256), 0, c.stream, hist);
     if (n) {
         dim3 g(G), b(B);
         switch (B) {
-        case 64: hipLaunchKernelGGL(hist256_kernel<64>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
-        case 128: hipLaunchKernelGGL(hist256_kernel<128>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
-        case 256: hipLaunchKernelGGL(hist256_kernel<256>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
-        case 512: hipLaunchKernelGGL(hist256_kernel<512>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
-        case 1024: hipLaunchKernelGGL(hist256_kernel<1024>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
+        case 64: dispatch(hist256_kernel<64>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
+        case 128: dispatch(hist256_kernel<128>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
+        case 256: dispatch(hist256_kernel<256>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
+        case 512: dispatch(hist256_kernel<512>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
+        case 1024: dispatch(hist256_kernel<1024>, g, b, c.dyn_shmem, c.stream, keys, hist, n, seg, vec); break;
         }
     }
     hipError_t e = hipGetLastError();

@@ -33,11 +33,11 @@ static void launch_c(uint32_t C, dim3 g, size_t dyn, hipStream_t s, const float*
                      uint32_t ny) {
     dim3 b(BX, BY);
     switch (C) {
-    case 1: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 1>), g, b, dyn, s, u, v, nx, ny); break;
-    case 2: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 2>), g, b, dyn, s, u, v, nx, ny); break;
-    case 4: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 4>), g, b, dyn, s, u, v, nx, ny); break;
-    case 8: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 8>), g, b, dyn, s, u, v, nx, ny); break;
-    case 16: hipLaunchKernelGGL((jacobi5_kernel<BX, BY, 16>), g, b, dyn, s, u, v, nx, ny); break;
+    case 1: dispatch((jacobi5_kernel<BX, BY, 1>), g, b, dyn, s, u, v, nx, ny); break;
+    case 2: dispatch((jacobi5_kernel<BX, BY, 2>), g, b, dyn, s, u, v, nx, ny); break;
+    case 4: dispatch((jacobi5_kernel<BX, BY, 4>), g, b, dyn, s, u, v, nx, ny); break;
+    case 8: dispatch((jacobi5_kernel<BX, BY, 8>), g, b, dyn, s, u, v, nx, ny); break;
+    case 16: dispatch((jacobi5_kernel<BX, BY, 16>), g, b, dyn, s, u, v, nx, ny); break;
     }
 }
 
@@ -69,24 +69,24 @@ int launch_jacobi5_f32(const LaunchCtx& c) {
         hipStream_t st = c.stream;
         switch (brow) {
         case 4:
-            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
-            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
+            if (vec) dispatch((jacobi5_v4_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
+            else dispatch((jacobi5_w_kernel<4, 1>), gv, bv, d, st, u, v, nx, ny);
             break;
         case 8:
-            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
-            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
+            if (vec) dispatch((jacobi5_v4_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
+            else dispatch((jacobi5_w_kernel<4, 2>), gv, bv, d, st, u, v, nx, ny);
             break;
         case 16:
-            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
-            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
+            if (vec) dispatch((jacobi5_v4_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
+            else dispatch((jacobi5_w_kernel<4, 4>), gv, bv, d, st, u, v, nx, ny);
             break;
         case 32:
-            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
-            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
+            if (vec) dispatch((jacobi5_v4_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
+            else dispatch((jacobi5_w_kernel<4, 8>), gv, bv, d, st, u, v, nx, ny);
             break;
         case 64:
-            if (vec) hipLaunchKernelGGL((jacobi5_v4_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
-            else hipLaunchKernelGGL((jacobi5_w_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
+            if (vec) dispatch((jacobi5_v4_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
+            else dispatch((jacobi5_w_kernel<4, 16>), gv, bv, d, st, u, v, nx, ny);
             break;
         }
         hipError_t e = hipGetLastError();

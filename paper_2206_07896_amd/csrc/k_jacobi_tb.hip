@@ -29,9 +29,9 @@ int launch_jacobi5t_f32(const LaunchCtx& c) {
     if ((uint64_t)c.grid.x * jt_width(halo) < nx || (uint64_t)c.grid.y * JT_H < ny) return SPMD_ERR_INVALID_DIM;
     const dim3 g(c.grid.x, c.grid.y), bl(JT_THREADS);
     if (sweeps <= 4)
-        hipLaunchKernelGGL((jacobi5_tb_kernel<4>), g, bl, c.dyn_shmem, c.stream, u, v, nx, ny, sweeps);
+        dispatch((jacobi5_tb_kernel<4>), g, bl, c.dyn_shmem, c.stream, u, v, nx, ny, sweeps);
     else
-        hipLaunchKernelGGL((jacobi5_tb_kernel<8>), g, bl, c.dyn_shmem, c.stream, u, v, nx, ny, sweeps);
+        dispatch((jacobi5_tb_kernel<8>), g, bl, c.dyn_shmem, c.stream, u, v, nx, ny, sweeps);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }

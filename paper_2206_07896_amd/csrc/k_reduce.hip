@@ -59,10 +59,10 @@ static void launch_reduce_b(uint32_t G, size_t dyn, hipStream_t s, const int32_t
     const uint32_t K = reduce_blocks_per_wg<B>(G, num_cus);
     const dim3 b(B);
     switch (K) {
-    case 1: hipLaunchKernelGGL(reduce_i32_kernel<B>, dim3(G), b, dyn, s, x, partials, out, n, seg, ws, err, vec); break;
-    case 2: hipLaunchKernelGGL((reduce_i32_pkernel<B, 2>), dim3((G + 1) / 2), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
-    case 4: hipLaunchKernelGGL((reduce_i32_pkernel<B, 4>), dim3((G + 3) / 4), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
-    default: hipLaunchKernelGGL((reduce_i32_pkernel<B, 8>), dim3((G + 7) / 8), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
+    case 1: dispatch(reduce_i32_kernel<B>, dim3(G), b, dyn, s, x, partials, out, n, seg, ws, err, vec); break;
+    case 2: dispatch((reduce_i32_pkernel<B, 2>), dim3((G + 1) / 2), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
+    case 4: dispatch((reduce_i32_pkernel<B, 4>), dim3((G + 3) / 4), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
+    default: dispatch((reduce_i32_pkernel<B, 8>), dim3((G + 7) / 8), b, dyn, s, x, partials, out, n, seg, G, ws, err, vec); break;
     }
 }
 

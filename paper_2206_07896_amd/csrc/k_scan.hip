@@ -71,7 +71,7 @@ static void launch_bi(uint32_t G, size_t dyn, hipStream_t s, const int32_t* x, i
         per_cu < 1)
         per_cu = 1;
     const uint32_t P = (uint32_t)std::min<uint64_t>(G, (uint64_t)per_cu * (uint64_t)num_cus);
-    hipLaunchKernelGGL((scan_i32_kernel<B, I>), dim3(P), dim3(B), dyn, s, x, y, n, G, ws, err, vec);
+    dispatch((scan_i32_kernel<B, I>), dim3(P), dim3(B), dyn, s, x, y, n, G, ws, err, vec);
 }
 
 template <int B>

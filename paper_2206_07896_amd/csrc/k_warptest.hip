@@ -76,7 +76,7 @@ int launch_warptest(const LaunchCtx& c) {
     auto pred = arg<const uint32_t*>(c.args, 1);
     auto out = arg<int32_t*>(c.args, 2);
     if (!val || !pred || !out) return SPMD_ERR_ARGS;
-    hipLaunchKernelGGL(warptest_kernel, dim3(c.grid.x), dim3(c.block.x), c.dyn_shmem, c.stream, val, pred, out);
+    dispatch(warptest_kernel, dim3(c.grid.x), dim3(c.block.x), c.dyn_shmem, c.stream, val, pred, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }
@@ -98,7 +98,7 @@ int launch_reverse_i32(const LaunchCtx& c) {
     if (c.grid.x != 1 || c.grid.y != 1 || c.grid.z != 1 || c.block.y != 1 || c.block.z != 1 || c.block.x != n)
         return SPMD_ERR_INVALID_DIM;
     if (c.dyn_shmem < 4ull * n) return SPMD_ERR_SHMEM;
-    hipLaunchKernelGGL(reverse_i32_kernel, dim3(1), dim3(n), c.dyn_shmem, c.stream, d, n);
+    dispatch(reverse_i32_kernel, dim3(1), dim3(n), c.dyn_shmem, c.stream, d, n);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }

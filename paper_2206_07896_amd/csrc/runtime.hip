@@ -24,6 +24,8 @@ namespace spmd {
 // current.
 __device__ uint32_t g_error_word[2];
 
+thread_local LaunchEvents g_launch_events = {nullptr, nullptr, false};
+
 namespace {
 
 constexpr int MAX_DEVICES = 64;
@@ -128,6 +130,21 @@ int spmd_launch(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem
     LaunchCtx c{kernel_id, grid, block, dyn_shmem, args, static_cast<hipStream_t>(stream), di};
     clear_stale_error();
     return ci->launch(c);
+}
+
+int spmd_launch_timed(int kernel_id, spmd_dim3 grid, spmd_dim3 block, size_t dyn_shmem, void** args, void* stream,
+                      void* start_event, void* stop_event) {
+    if (!stop_event) return SPMD_ERR_ARGS;
+    g_launch_events = {static_cast<hipEvent_t>(start_event), static_cast<hipEvent_t>(stop_event), false};
+    const int rc = spmd_launch(kernel_id, grid, block, dyn_shmem, args, stream);
+    const bool used = g_launch_events.used;
+    g_launch_events = {nullptr, nullptr, false};
+    if (rc != SPMD_OK || used) return rc;
+    // nothing was enqueued: an empty span
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = start_event ? hipEventRecord(static_cast<hipEvent_t>(start_event), s) : hipSuccess;
+    if (e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(stop_event), s);
+    return e == hipSuccess ? SPMD_OK : hip_fail(e);
 }
 
 size_t spmd_workspace_size(int kernel_id, spmd_dim3 grid, spmd_dim3 block, uint64_t n) {

@@ -1,7 +1,9 @@
 """Tensor-level helpers over :func:`launch`: allocate outputs and workspace
 with PyTorch, pick the launch shape, enqueue.  They do no arithmetic of
 their own.  All tensors must live on the current HIP device; int32 tensors
-carry uint32 data bit for bit (keys, histogram counts).
+carry uint32 data bit for bit (keys, histogram counts).  The single-launch
+helpers take ``events=(start, stop)`` (from :func:`timing_events`) to time
+their launch's kernels on the device (spmd_launch_timed).
 """
 
 from __future__ import annotations
@@ -30,7 +32,7 @@ def workspace(kernel, grid, block, n: int, device=None) -> torch.Tensor:
 
 
 def reduce_i32(x: torch.Tensor, grid: int = 4096, block: int = 256, partials=None, out=None, ws=None,
-               dyn_shmem: int | None = None, stream=None):
+               dyn_shmem: int | None = None, stream=None, events=None):
     _check_dev(x)
     n = x.numel()
     if partials is None:
@@ -40,7 +42,7 @@ def reduce_i32(x: torch.Tensor, grid: int = 4096, block: int = 256, partials=Non
     if ws is None:
         ws = workspace(REDUCE_I32, grid, block, n, x.device)
     shm = 4 * block if dyn_shmem is None else dyn_shmem
-    launch(REDUCE_I32, grid, block, shm, [x, partials, out, n, ws], stream)
+    launch(REDUCE_I32, grid, block, shm, [x, partials, out, n, ws], stream, events)
     return partials, out
 
 
@@ -48,7 +50,7 @@ def scan_grid(n: int, block: int = 512, items: int = 16) -> int:
     return max(1, _cdiv(n, block * items))
 
 
-def scan_i32(x: torch.Tensor, block: int = 512, items: int = 16, y=None, ws=None, stream=None):
+def scan_i32(x: torch.Tensor, block: int = 512, items: int = 16, y=None, ws=None, stream=None, events=None):
     _check_dev(x)
     n = x.numel()
     grid = scan_grid(n, block, items)
@@ -56,7 +58,7 @@ def scan_i32(x: torch.Tensor, block: int = 512, items: int = 16, y=None, ws=None
         y = torch.empty_like(x)
     if ws is None:
         ws = workspace(SCAN_I32, grid, block, n, x.device)
-    launch(SCAN_I32, grid, block, 0, [x, y, n, ws], stream)
+    launch(SCAN_I32, grid, block, 0, [x, y, n, ws], stream, events)
     return y
 
 
@@ -65,7 +67,7 @@ def compact_grid(n: int, block: int = 256, items: int = 16) -> int:
 
 
 def compact_i32(x: torch.Tensor, t: int, block: int = 256, items: int = 16, y=None, count=None, ws=None,
-                stream=None):
+                stream=None, events=None):
     """Elements of x greater than t, in order: returns (y, count); y[:count]
     holds them."""
     _check_dev(x)
@@ -77,15 +79,15 @@ def compact_i32(x: torch.Tensor, t: int, block: int = 256, items: int = 16, y=No
         count = torch.zeros(1, dtype=torch.int32, device=x.device)
     if ws is None:
         ws = workspace(COMPACT_I32, grid, block, n, x.device)
-    launch(COMPACT_I32, grid, block, 0, [x, y, count, n, int(t) & 0xFFFFFFFF, ws], stream)
+    launch(COMPACT_I32, grid, block, 0, [x, y, count, n, int(t) & 0xFFFFFFFF, ws], stream, events)
     return y, count
 
 
-def hist256_u32(keys: torch.Tensor, grid: int = 256, block: int = 1024, hist=None, stream=None):
+def hist256_u32(keys: torch.Tensor, grid: int = 256, block: int = 1024, hist=None, stream=None, events=None):
     _check_dev(keys)
     if hist is None:
         hist = torch.empty(256, dtype=torch.int32, device=keys.device)
-    launch(HIST256_U32, grid, block, 0, [keys, hist, keys.numel()], stream)
+    launch(HIST256_U32, grid, block, 0, [keys, hist, keys.numel()], stream, events)
     return hist
 
 
@@ -94,12 +96,12 @@ def jacobi_grid(nx: int, ny: int, block=(16, 16), cells: int = 1):
     return (_cdiv(nx, bx), _cdiv(ny, by * cells))
 
 
-def jacobi5_f32(u: torch.Tensor, out=None, block=(16, 16), cells: int = 1, stream=None):
+def jacobi5_f32(u: torch.Tensor, out=None, block=(16, 16), cells: int = 1, stream=None, events=None):
     _check_dev(u)
     ny, nx = u.shape
     if out is None:
         out = torch.empty_like(u)
-    launch(JACOBI5_F32, jacobi_grid(nx, ny, block, cells), (block[0], block[1], 1), 0, [u, out, nx, ny], stream)
+    launch(JACOBI5_F32, jacobi_grid(nx, ny, block, cells), (block[0], block[1], 1), 0, [u, out, nx, ny], stream, events)
     return out
 
 
@@ -122,13 +124,13 @@ def jacobi5t_grid(nx: int, ny: int, sweeps: int):
     return (_cdiv(nx, 256 - 2 * h), _cdiv(ny, 64))
 
 
-def jacobi5t_f32(u: torch.Tensor, sweeps: int, out=None, stream=None):
+def jacobi5t_f32(u: torch.Tensor, sweeps: int, out=None, stream=None, events=None):
     """``sweeps`` (1..8) sweeps in one launch (SPMD_JACOBI5T_F32)."""
     _check_dev(u)
     ny, nx = u.shape
     if out is None:
         out = torch.empty_like(u)
-    launch(JACOBI5T_F32, jacobi5t_grid(nx, ny, sweeps), (256, 1, 1), 0, [u, out, nx, ny, sweeps], stream)
+    launch(JACOBI5T_F32, jacobi5t_grid(nx, ny, sweeps), (256, 1, 1), 0, [u, out, nx, ny, sweeps], stream, events)
     return out
 
 
@@ -147,14 +149,14 @@ def jacobi5t_sweeps(u: torch.Tensor, sweeps: int, per_launch: int = 4, scratch=N
     return src
 
 
-def gemm_f32(A: torch.Tensor, B: torch.Tensor, C=None, tile: int = 128, stream=None):
+def gemm_f32(A: torch.Tensor, B: torch.Tensor, C=None, tile: int = 128, stream=None, events=None):
     _check_dev(A, B)
     M, K = A.shape
     K2, N = B.shape
     assert K == K2
     if C is None:
         C = torch.empty((M, N), dtype=torch.float32, device=A.device)
-    launch(GEMM_F32, (_cdiv(N, tile), _cdiv(M, tile)), 256, 0, [A, B, C, M, N, K], stream)
+    launch(GEMM_F32, (_cdiv(N, tile), _cdiv(M, tile)), 256, 0, [A, B, C, M, N, K], stream, events)
     return C
 
 

@@ -95,6 +95,22 @@ def test_null_args(spmd):
     assert rc == -4
 
 
+def test_launch_timed_validation(spmd):
+    """spmd_launch_timed refuses a null stop event before any device call, and
+    passes spmd_launch's own refusals through without touching the events
+    (here stand-in handles that are never dereferenced)."""
+    lib = spmd.lib()
+    arr = (ctypes.c_void_p * 5)()
+    argp = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+    d1, d64 = spmd._dim3(1), spmd._dim3(64)
+    assert lib.spmd_launch_timed(spmd.REDUCE_I32, d1, d64, 0, argp, None, None, None) == -4
+    assert lib.spmd_launch_timed(spmd.REDUCE_I32, d1, d64, 0, argp, None, 16, None) == -4
+    assert lib.spmd_launch_timed(99, d1, d64, 0, argp, None, None, 32) == -1  # a null start event is allowed
+    assert lib.spmd_launch_timed(99, d1, d64, 0, argp, None, 16, 32) == -1
+    assert lib.spmd_launch_timed(spmd.REDUCE_I32, spmd._dim3((0, 1, 1)), d64, 0, argp, None, 16, 32) == -2
+    assert lib.spmd_launch_timed(spmd.REDUCE_I32, d1, d64, 0, argp, None, 16, 32) == -4  # null arguments
+
+
 def _raw_noalloc(spmd, kid, grid, block, args):
     argp = None
     if args is not None:

@@ -206,6 +206,49 @@ def test_hist(spmd, n, grid, block):
         assert np.array_equal(host(h, np.uint32), want), rep
 
 
+def test_launch_timed(spmd):
+    """spmd_launch_timed gives spmd_launch's results; its event span, bound
+    to the launch's first and last kernel dispatch (the histogram launch has
+    two: clear, then count), is positive and lies inside a pair of events
+    recorded around the calls, as does the span to a launch that binds its
+    stop event alone; a launch with nothing to do records its events
+    together; a refused launch raises."""
+    import torch
+
+    n = (1 << 20) + 77
+    x = synth.uniform_int32(synth.SEED_SCAN + 11, n, -(2**31), 2**31 - 1)
+    keys = synth.zipf_u32(synth.SEED_HIST + 11, n)
+    want = oracle.scan_i32(x, block=64, items=4)
+    want_h = oracle.hist256_u32(keys, 256, 1024)
+    xt, kt = dev(x), dev(keys)
+    for rep in range(3):
+        say("launch_timed scan 512x16 and hist 256x1024", n, rep)
+        ev = spmd.timing_events(5)
+        o0, o1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        o0.record()
+        y = spmd.ops.scan_i32(xt, 512, 16, events=ev[0:2])
+        h = spmd.ops.hist256_u32(kt, 256, 1024, events=ev[2:4])
+        y2 = spmd.ops.scan_i32(xt, 512, 16, events=(None, ev[4]))  # stop event only
+        o1.record()
+        o1.synchronize()
+        spmd.sync()
+        assert np.array_equal(host(y), want) and np.array_equal(host(y2), want)
+        assert np.array_equal(host(h, np.uint32), want_h)
+        t_scan, t_hist, t_out = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), o0.elapsed_time(o1)
+        t_scan2 = ev[3].elapsed_time(ev[4])  # from the histogram's end to the second scan's end
+        assert t_scan > 0 and t_hist > 0 and t_scan2 > 0, (t_scan, t_hist, t_scan2)
+        assert t_scan + t_hist + t_scan2 <= t_out + 0.002, (t_scan, t_hist, t_scan2, t_out)
+    say("launch_timed: empty scan, refused histogram")
+    ev = spmd.timing_events(2)
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    spmd.ops.scan_i32(empty, 512, 16, events=ev)
+    ev[1].synchronize()
+    assert ev[0].elapsed_time(ev[1]) >= 0
+    with pytest.raises(spmd.SpmdError):
+        spmd.ops.hist256_u32(kt, 256, 2048, events=spmd.timing_events(2))
+    spmd.sync()
+
+
 def skewed_keys(n, alpha, perm, seed):
     """Bounded Zipf(alpha) bins (or every key in bin 7 for alpha "one"),
     optionally through the seeded bin permutation, random upper bits."""
