@@ -119,7 +119,10 @@ def test_reduce_wrapping_and_unaligned(spmd):
 @pytest.mark.parametrize("n,block,items", [(1, 64, 1), (100, 64, 1), (5000, 64, 4), (8193, 128, 8), (70001, 512, 16),
                                            (200000, 1024, 32), (123457, 256, 2), (300001, 512, 64),
                                            (65536 * 3 + 17, 256, 64), (40000, 512, 32),
-                                           (65536 * 5 + 3, 512, 128), (100001, 256, 128), (1000, 64, 128)])
+                                           (65536 * 5 + 3, 512, 128), (100001, 256, 128), (1000, 64, 128),
+                                           # 16384 and 32768 tiles of 64 and 128 elements, thousands of
+                                           # blocks resident at once: look-backs that cross many windows
+                                           (1 << 20, 64, 1), ((1 << 22) - 5, 64, 2)])
 def test_scan(spmd, n, block, items):
     say("scan", n, block, items)
     x = synth.uniform_int32(synth.SEED_SCAN + n, n, -(2**31), 2**31 - 1)
@@ -592,7 +595,7 @@ def test_maximum_size_closed_forms(spmd):
                                              (8193, 128, 8, 500), (70001, 256, 16, 0),
                                              (200000, 1024, 32, -900), (123457, 512, 2, 999),
                                              (4096 * 16 * 3, 256, 16, 0), (300001, 512, 64, 0),
-                                             (65536 * 3 + 17, 256, 64, -3)])
+                                             (65536 * 3 + 17, 256, 64, -3), (1 << 20, 64, 1, 0)])
 def test_compact(spmd, n, block, items, t):
     import torch
 
