@@ -116,7 +116,7 @@ def main():
                     help="run only the timed step (for profiler runs): no extras, mixed queue or CPU baseline")
     ap.add_argument("--only-gemm", action="store_true",
                     help="run only the fp32 GEMM at tiles 64, 128 and 256, a few launches each (for profiler runs)")
-    ap.add_argument("--only", choices=("reduce", "jacobi", "compact", "chain", "hist", "mixed"), default=None,
+    ap.add_argument("--only", choices=("reduce", "scan", "jacobi", "compact", "chain", "hist", "mixed"), default=None,
                     help="run only one other workload, then three 256 MiB calibration copies (for profiler runs)")
     ap.add_argument("--gemm-n", type=int, default=4096, help="M = N = K of --only-gemm")
     args = ap.parse_args()
@@ -138,7 +138,8 @@ def main():
         print(json.dumps({"only_gemm": gemm_workloads(spmd, synth, reps=5, n=args.gemm_n)}), flush=True)
         return
     if args.only:
-        fn = {"reduce": reduce_workloads, "jacobi": jacobi_workloads, "compact": compact_workloads,
+        fn = {"reduce": reduce_workloads, "scan": scan_size_workloads, "jacobi": jacobi_workloads,
+              "compact": compact_workloads,
               "chain": chain_workloads, "hist": hist_contention_workloads,
               "mixed": lambda sp, _sy: mixed_queue(sp, args.mixed_count, reps=3)}[args.only]
         out = fn(spmd, synth)
@@ -328,6 +329,7 @@ def extra_workloads(spmd, synth):
     """Per-kernel figures of the other workloads (not part of the step)."""
     res = copy_reference()
     res.update(vendor_scan_reference(synth))
+    res.update(scan_size_workloads(spmd, synth))
     res.update(reduce_workloads(spmd, synth))
     res.update(jacobi_workloads(spmd, synth))
     res.update(hist_contention_workloads(spmd, synth))
@@ -366,6 +368,46 @@ def vendor_scan_reference(synth):
                                                   "frac_hbm": round(8 * n / ms / 1e6 / HBM_PEAK_GBS, 4)}}
     del x, y
     torch.cuda.empty_cache()
+    return res
+
+
+def scan_size_workloads(spmd, synth):
+    """SCAN_I32 at the step's launch shape (512 x 128) on 2^28 and 2^30
+    elements (U[0,100], generated on the device): 16 and 64 rounds of tiles
+    per persistent block instead of 4, so the end of the launch, when
+    blocks run out of tiles one after another, weighs less.  Timed with
+    events bound to each launch's dispatch; every output is checked with
+    the scan's defining identity y[i] - y[i-1] = x[i] (mod 2^32) on the
+    device."""
+    import torch
+
+    res = {}
+    for lg, reps in ((28, 10), (30, 4)):
+        n = 1 << lg
+        log(f"scan 2^{lg}")
+        x = torch.empty(n, dtype=torch.int32, device="cuda")
+        spmd.batch.synth_uniform_i32(x, synth.SEED_SCAN, 0, 100)
+        y = torch.empty_like(x)
+        grid = spmd.ops.scan_grid(n, SCAN_BLOCK, SCAN_ITEMS)
+        ws = spmd.ops.workspace(spmd.SCAN_I32, grid, SCAN_BLOCK, n)
+        for _ in range(2):
+            spmd.ops.scan_i32(x, SCAN_BLOCK, SCAN_ITEMS, y=y, ws=ws)
+        spans = []
+        for _ in range(reps):
+            ev = spmd.timing_events(2)
+            spmd.ops.scan_i32(x, SCAN_BLOCK, SCAN_ITEMS, y=y, ws=ws, events=(ev[0], ev[1]))
+            spans.append(ev)
+        torch.cuda.synchronize()
+        spmd.sync()
+        ok = bool(y[0].item() == x[0].item()) and bool(torch.equal(y[1:] - y[:-1], x[1:]))
+        assert ok, f"scan 2^{lg}: y[i] - y[i-1] != x[i]"
+        ms = sorted(a.elapsed_time(b) for a, b in spans)[reps // 2]
+        b = 8 * n
+        res[f"scan_i32 2^{lg} b{SCAN_BLOCK} i{SCAN_ITEMS}"] = {
+            "us": round(ms * 1e3, 2), "GB/s": round(b / ms / 1e6, 1), "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "timing": f"median of {reps} launches, HIP events bound to each launch's dispatch", "checked": ok}
+        del x, y, ws
+        torch.cuda.empty_cache()
     return res
 
 
