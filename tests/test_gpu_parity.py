@@ -190,6 +190,31 @@ def test_scan_workload_size(spmd, items):
         assert np.array_equal(got[:1 << 20].view(np.int32), want_prefix), rep
 
 
+@pytest.mark.parametrize("lg", [28, 30])
+def test_scan_large_sizes(spmd, lg):
+    """The measured step's launch shape (512 x 128) on 2^28 and 2^30 int32
+    U[0, 100] generated on the device (the host generator's stream, which
+    test_device_generator_matches_host pins): 16 and 64 tiles per persistent
+    block.  Checked over every element on the device by the complete
+    invariant, the last element by the closed form (the sum mod 2^32), and a
+    2^20 prefix against the oracle."""
+    import torch
+
+    n = 1 << lg
+    say("scan", f"2^{lg}", "block 512 items 128")
+    xt = torch.empty(n, dtype=torch.int32, device="cuda")
+    spmd.batch.synth_uniform_i32(xt, synth.SEED_SCAN, 0, 100)
+    y = spmd.ops.scan_i32(xt, 512, 128)
+    spmd.sync()
+    assert int(y[0].item()) == int(xt[0].item())
+    assert torch.equal(y[1:] - y[:-1], xt[1:])  # int32 arithmetic wraps: mod 2^32
+    assert int(y[-1].item()) % 2**32 == int(xt.sum(dtype=torch.int64).item()) % 2**32
+    x_prefix = synth.uniform_int32(synth.SEED_SCAN, 1 << 20, 0, 100)
+    assert np.array_equal(host(y[: 1 << 20]), oracle.scan_i32(x_prefix, 512, 64))
+    del xt, y
+    torch.cuda.empty_cache()
+
+
 # --------------------------------------------------------------------------
 # HIST256
 # --------------------------------------------------------------------------
