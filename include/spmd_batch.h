@@ -58,9 +58,14 @@ typedef struct {
  * `ny` rows for JACOBI (1 otherwise).  `in` is x / keys / u; `out` is the
  * int32 total (REDUCE), y[n] (SCAN), the 256 uint32 bins (HIST, overwritten)
  * or u_next (JACOBI, one sweep).  `out` may not overlap `in`
- * (SPMD_ERR_ARGS): a plan may run an instance more than once.  `block_dim`
- * is the blockDim the instance was written for; it is a feature of the
- * instance, not a constraint on its schedule. */
+ * (SPMD_ERR_ARGS): a plan may run an instance more than once.  The
+ * instances of one dependency level (all of them, without dependencies)
+ * run concurrently and in no order, like kernels on different streams: an
+ * instance's `out` must not overlap the `in` or `out` of another instance
+ * of its level.  The plan does not check this; two HIST instances of one
+ * level that share their bins leave the sum of both histograms there.
+ * `block_dim` is the blockDim the instance was written for; it is a
+ * feature of the instance, not a constraint on its schedule. */
 typedef struct {
     int32_t kernel_id;
     uint32_t n;
