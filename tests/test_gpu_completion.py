@@ -134,3 +134,52 @@ def test_error_word_is_per_device(spmd):
     assert e.value.kind == "DEVICE"
     spmd.sync(side)
     spmd.sync()
+
+
+def test_concurrent_persistent_launches(spmd):
+    """Three launches whose blocks wait on each other, each sized to fill
+    every compute unit, enqueued on three streams at once so that they
+    share the device: a scan (512 x 128), a compaction (1024 x 32) and a
+    reduction.  Tiles are handed out by each launch's own ticket, so a
+    block waits only for tiles that running blocks of its launch hold, and
+    every launch completes whatever share of the device the others leave it
+    (the queue's forward-progress argument, Section IV).  Five rounds on
+    the same workspaces; every result checked."""
+    import torch
+
+    n = 1 << 24
+    xs = synth.uniform_int32(synth.SEED_SCAN, n, 0, 100)
+    xc = synth.uniform_int32(0xC0 + n, n, -1000, 1000)
+    xr = synth.uniform_int32(synth.SEED_REDUCE, n, -1000, 1000)
+    want_c = oracle.compact_i32(xc, 0)
+    want_r = int(xr.astype(np.int64).sum()) % 2**32
+    want_s_prefix = oracle.scan_i32(xs[: 1 << 18], 512, 64)
+    d_s, d_c, d_r = (torch.from_numpy(a).cuda() for a in (xs, xc, xr))
+    ws_s = spmd.ops.workspace(spmd.SCAN_I32, spmd.ops.scan_grid(n, 512, 128), 512, n)
+    ws_c = spmd.ops.workspace(spmd.COMPACT_I32, spmd.ops.compact_grid(n, 1024, 32), 1024, n)
+    ws_r = spmd.ops.workspace(spmd.REDUCE_I32, 4096, 256, n)
+    y_s = torch.empty_like(d_s)
+    y_c = torch.empty_like(d_c)
+    cnt = torch.empty(1, dtype=torch.int32, device="cuda")
+    part = torch.empty(4096, dtype=torch.int32, device="cuda")
+    tot = torch.empty(1, dtype=torch.int32, device="cuda")
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for rnd in range(5):
+        say("concurrent scan + compaction + reduce, round", rnd)
+        y_s.fill_(-1)
+        cnt.fill_(-1)
+        tot.fill_(0)
+        torch.cuda.synchronize()
+        spmd.ops.scan_i32(d_s, 512, 128, y=y_s, ws=ws_s, stream=streams[0])
+        spmd.ops.compact_i32(d_c, 0, 1024, 32, y=y_c, count=cnt, ws=ws_c, stream=streams[1])
+        spmd.ops.reduce_i32(d_r, 4096, 256, part, tot, ws_r, stream=streams[2])
+        for s in streams:
+            s.synchronize()
+        spmd.sync()
+        assert int(y_s[0].item()) == int(d_s[0].item()), rnd
+        assert torch.equal(y_s[1:] - y_s[:-1], d_s[1:]), rnd
+        assert np.array_equal(y_s[: 1 << 18].cpu().numpy(), want_s_prefix), rnd
+        m = int(cnt.item())
+        assert m == want_c.size, (rnd, m)
+        assert np.array_equal(y_c[:m].cpu().numpy(), want_c), rnd
+        assert int(tot.item()) % 2**32 == want_r, rnd
