@@ -335,7 +335,9 @@ def test_jacobi_one_sweep(spmd, block, cells):
     # Block rows of 4 to 64 rows run 256 columns per workgroup: nx % 4 == 0 with aligned rows
     # takes the 16-byte form, any other nx the general-width form (four columns 64 apart);
     # block rows of 1 or 2 rows take the scalar body.
-    for (ny, nx) in [(33, 70), (130, 257), (3, 3), (33, 68), (130, 520), (5, 4), (64, 260)]:
+    # degenerate grids last: one row or column, or two (every cell a border cell, copied)
+    for (ny, nx) in [(33, 70), (130, 257), (3, 3), (33, 68), (130, 520), (5, 4), (64, 260),
+                     (1, 1), (1, 300), (300, 1), (2, 2), (2, 513), (1, 4), (2, 260)]:
         say("jacobi", ny, nx, block, cells)
         u = synth.uniform_f32(synth.SEED_JACOBI + nx, ny * nx).reshape(ny, nx)
         want = oracle.jacobi5_f32(u, 16, 16)
